@@ -1,0 +1,258 @@
+"""Pins on the oracle's TRiSK right-hand side (Appendix B of the paper).
+
+Each test checks the oracle against something fixed outside its own code:
+closed forms of the discrete operators for fields they differentiate exactly,
+conservation identities, the lake at rest, orientation invariance, stencil
+locality, and the linear inertia-gravity wave of the rotating shallow water
+equations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2106_07154_amd.inputs import igw_parameters, igw_state, periodic_hex_mesh
+
+G = 9.81
+
+
+def _interior(m, x, y, pad):
+    return (x > pad) & (x < m.Lx - pad) & (y > pad) & (y < m.Ly - pad)
+
+
+def _edge_of_cells_interior(m, pad):
+    ok = _interior(m, m.xCell, m.yCell, pad)
+    return ok[m.cellsOnEdge[:, 0]] & ok[m.cellsOnEdge[:, 1]]
+
+
+# ---------------------------------------------------------------- weights
+def test_weights_regular_hex_pattern(hex16):
+    """On a regular hexagon every kite is A/6, so |w_{e,e'}| = |m/6 - 1/2| for an
+    edge m vertex steps away: the pattern 1/3, 1/6, 0, 1/6, 1/3 per cell."""
+    o = Oracle(hex16)
+    for e in range(0, hex16.nEdges, 7):
+        ee, w = o.weights(e)
+        assert len(ee) == 10
+        np.testing.assert_allclose(sorted(np.abs(w)),
+                                   sorted([1 / 3, 1 / 6, 0.0, 1 / 6, 1 / 3] * 2), atol=1e-15)
+
+
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+def test_weights_antisymmetric(meshname, request):
+    """w_{e,e'} = -w_{e',e}: the property behind energy conservation."""
+    m = request.getfixturevalue(meshname)
+    o = Oracle(m)
+    W = {}
+    for e in range(m.nEdges):
+        ee, w = o.weights(e)
+        assert len(ee) == m.nEdgesOnCell[m.cellsOnEdge[e]].sum() - 2
+        for a, b in zip(ee, w):
+            W[(e, int(a))] = b
+    worst = max(abs(W[(e, a)] + W[(a, e)]) for (e, a) in W)
+    assert worst < 1e-14
+
+
+def test_perp_reconstructs_uniform_flux(hex16):
+    """F_perp_e = (k x F) . n_e exactly for uniform F on a regular hexagonal mesh:
+    the counter-clockwise reading of the weight traversal gives the rotation
+    k x F that the continuous PV term -q F_perp needs (Appendix A)."""
+    m = hex16
+    o = Oracle(m)
+    for U in ([1.0, 0.0], [0.3, -2.0]):
+        U = np.array(U)
+        _, _, _, fp = o.diag_fields(np.ones(m.nCells), m.normalEdge @ U)
+        kxF = np.array([-U[1], U[0]])
+        np.testing.assert_allclose(fp, m.normalEdge @ kxF, atol=1e-14)
+
+
+# ---------------------------------------------------------------- K, div, grad, curl
+def test_kinetic_energy_uniform_flow(hex16):
+    m = hex16
+    U = np.array([1.7, -0.4])
+    K, _, _, _ = Oracle(m).diag_fields(np.full(m.nCells, 10.0), m.normalEdge @ U)
+    np.testing.assert_allclose(K, 0.5 * U @ U, rtol=1e-14)
+
+
+def test_divergence_of_linear_field(hex16):
+    """Constant h, u from a linear vector field: H_i = -H div V exactly."""
+    m = hex16
+    A = np.array([[2e-6, -1e-6], [3e-6, 5e-7]])
+    c = np.array([0.1, -0.2])
+    V = (np.stack([m.xEdge, m.yEdge], 1) @ A.T) + c
+    u = (V * m.normalEdge).sum(1)
+    H = 1000.0
+    dh, _ = Oracle(m).rhs(np.full(m.nCells, H), u)
+    ok = _interior(m, m.xCell, m.yCell, 2e4)
+    np.testing.assert_allclose(dh[ok], -H * (A[0, 0] + A[1, 1]), rtol=1e-10)
+
+
+def test_gradient_of_linear_height(hex16):
+    """u = 0, h linear: U_e = -g (grad h) . n_e exactly."""
+    m = hex16
+    a = np.array([1e-5, -2e-5])
+    h = 1000.0 + np.stack([m.xCell, m.yCell], 1) @ a
+    _, du = Oracle(m).rhs(h, np.zeros(m.nEdges))
+    ok = _edge_of_cells_interior(m, 2e4)
+    np.testing.assert_allclose(du[ok], -G * (m.normalEdge[ok] @ a), rtol=1e-10, atol=1e-16)
+
+
+@pytest.mark.parametrize("meshname", ["hex16", "irregular"])
+def test_vorticity_of_linear_field(meshname, request):
+    """Circulation over the dual triangle is exact for linear fields (Stokes with
+    the midpoint rule): zeta_v = dV/dx - dU/dy."""
+    m = request.getfixturevalue(meshname)
+    A = np.array([[1e-6, -4e-6], [3e-6, 2e-6]])
+    V = np.stack([m.xEdge, m.yEdge], 1) @ A.T
+    u = (V * m.normalEdge).sum(1)
+    _, _, zeta, _ = Oracle(m).diag_fields(np.full(m.nCells, 100.0), u)
+    cx = m.xCell[m.cellsOnVertex]
+    cy = m.yCell[m.cellsOnVertex]
+    pad = 3e4
+    ok = (_interior(m, cx, cy, pad)).all(1)
+    assert ok.sum() > 50
+    np.testing.assert_allclose(zeta[ok], A[1, 0] - A[0, 1], rtol=1e-9)
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+def test_lake_at_rest(meshname, request):
+    m = request.getfixturevalue(meshname).copy()
+    rng = np.random.default_rng(4)
+    m.bottom = 30.0 * rng.standard_normal(m.nCells)
+    h = 1000.0 - m.bottom
+    dh, du = Oracle(m).rhs(h, np.zeros(m.nEdges))
+    assert np.abs(dh).max() == 0.0
+    assert np.abs(du).max() < 1e-12 * G * 1000.0 / m.dcEdge.min()
+
+
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+def test_energy_and_mass_identities(meshname, request):
+    """sum_i A_i (K_i + g(h_i+b_i)) H_i + sum_e l_e d_e h_e u_e U_e = 0 and
+    sum_i A_i H_i = 0 for any state: the semi-discrete system conserves energy
+    and mass on a periodic mesh."""
+    m = request.getfixturevalue(meshname)
+    o = Oracle(m)
+    rng = np.random.default_rng(7)
+    for trial in range(3):
+        h = 1000.0 + 5.0 * rng.standard_normal(m.nCells)
+        u = rng.standard_normal(m.nEdges)
+        dh, du = o.rhs(h, u)
+        K, _, _, _ = o.diag_fields(h, u)
+        he = 0.5 * (h[m.cellsOnEdge[:, 0]] + h[m.cellsOnEdge[:, 1]])
+        t1 = m.areaCell * (K + G * (h + m.bottom)) * dh
+        t2 = m.dvEdge * m.dcEdge * he * u * du
+        scale = np.abs(t1).sum() + np.abs(t2).sum()
+        assert abs(t1.sum() + t2.sum()) < 1e-13 * scale
+        tm = m.areaCell * dh
+        assert abs(tm.sum()) < 1e-14 * np.abs(tm).sum()
+
+
+def test_energy_identity_fails_for_planted_sign_error(hex16, monkeypatch):
+    """The identity is sensitive: flipping the sign of the K-gradient breaks it."""
+    m = hex16
+    o = Oracle(m)
+    rng = np.random.default_rng(8)
+    h = 1000.0 + 5.0 * rng.standard_normal(m.nCells)
+    u = rng.standard_normal(m.nEdges)
+    dh, du = o.rhs(h, u)
+    K, _, _, _ = o.diag_fields(h, u)
+    c0, c1 = m.cellsOnEdge[:, 0], m.cellsOnEdge[:, 1]
+    du_bad = du + 2.0 * (K[c1] - K[c0]) / m.dcEdge  # grad K with the wrong sign
+    he = 0.5 * (h[c0] + h[c1])
+    t1 = m.areaCell * (K + G * h) * dh
+    t2 = m.dvEdge * m.dcEdge * he * u * du_bad
+    assert abs(t1.sum() + t2.sum()) > 1e-6 * (np.abs(t1).sum() + np.abs(t2).sum())
+
+
+def test_orientation_flip_invariance(irregular):
+    """n_e is arbitrary: flipping it (and u_e) changes only the sign of U_e."""
+    m = irregular
+    rng = np.random.default_rng(9)
+    flip = rng.random(m.nEdges) < 0.4
+    mf = m.copy()
+    mf.cellsOnEdge[flip] = mf.cellsOnEdge[flip][:, ::-1]
+    mf.verticesOnEdge[flip] = mf.verticesOnEdge[flip][:, ::-1]
+    mf.normalEdge[flip] *= -1.0
+    h = 1000.0 + rng.standard_normal(m.nCells)
+    u = rng.standard_normal(m.nEdges)
+    uf = np.where(flip, -u, u)
+    dh, du = Oracle(m).rhs(h, u)
+    dhf, duf = Oracle(mf).rhs(h, uf)
+    np.testing.assert_allclose(dhf, dh, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(duf, np.where(flip, -du, du), rtol=1e-11, atol=1e-15)
+
+
+def test_stencil_locality(hex8):
+    """U_e reads h only on CE(e) and their neighbours; H_i reads u only on EC(i).
+    This two-ring reach is what region-restricted evaluation relies on."""
+    m = hex8
+    o = Oracle(m)
+    rng = np.random.default_rng(10)
+    h = 1000.0 + rng.standard_normal(m.nCells)
+    u = rng.standard_normal(m.nEdges)
+    dh0, du0 = o.rhs(h, u)
+    nbr = [set(m.cellsOnCell[i, :m.nEdgesOnCell[i]]) | {i} for i in range(m.nCells)]
+    for j in range(m.nCells):
+        hp = h.copy()
+        hp[j] += 0.5
+        _, du = o.rhs(hp, u)
+        changed = np.nonzero(du != du0)[0]
+        for e in changed:
+            c0, c1 = m.cellsOnEdge[e]
+            assert j in nbr[c0] | nbr[c1]
+    for e in range(m.nEdges):
+        up = u.copy()
+        up[e] += 0.5
+        dh, _ = o.rhs(h, up)
+        changed = set(np.nonzero(dh != dh0)[0])
+        assert changed <= set(m.cellsOnEdge[e])
+
+
+# ---------------------------------------------------------------- linear wave
+def test_igw_second_order_in_space_and_polarisation():
+    """Linear inertia-gravity wave, omega^2 = f^2 + gH(k^2+l^2): the discrete
+    solution converges to the closed form at second order in dc, and the
+    velocity has the polarisation of f > 0 (the PV-term sign), not of f < 0."""
+    errs = []
+    for n in (16, 32, 64):
+        dc = 640e3 / n
+        m = periodic_hex_mesh(n, n, dc, f0=1e-4)
+        o = Oracle(m)
+        p = igw_parameters(m, amp=1e-3)
+        h0, u0 = igw_state(m, p, 0.0)
+        T = 2000.0
+        ns = int(math.ceil(T / (0.1 * dc / 99.0)))
+        h, u = o.rk4(h0, u0, T / ns, ns)
+        he, ue = igw_state(m, p, T)
+        errs.append((np.abs(h - he).max() / p.amp, np.abs(u - ue).max() / np.abs(ue).max()))
+        pw = igw_parameters(m, amp=1e-3, f=-1e-4)
+        _, uw = igw_state(m, pw, T)
+        assert np.abs(u - uw).max() / np.abs(ue).max() > 0.08
+    for (a, b), (c, d) in zip(errs[:-1], errs[1:]):
+        assert a / c > 3.5 and b / d > 3.5
+    assert errs[-1][0] < 0.01 and errs[-1][1] < 0.01
+
+
+@pytest.mark.parametrize("meshname", ["hex16", "irregular"])
+def test_diagnostic_energy_is_conserved_by_rhs(meshname, request):
+    """The diagnostic total energy sum_i A_i (h_i K_i + g(h_i^2/2 + h_i b_i)) is
+    the invariant of the semi-discrete system: its derivative along R(x),
+    taken by central differences of the diagnostic itself, vanishes."""
+    m = request.getfixturevalue(meshname)
+    o = Oracle(m)
+    rng = np.random.default_rng(17)
+    h = 1000.0 + 5.0 * rng.standard_normal(m.nCells)
+    u = rng.standard_normal(m.nEdges)
+    dh, du = o.rhs(h, u)
+    eps = 1e-3
+    ep = o.diagnostics(h + eps * dh, u + eps * du)[1]
+    em = o.diagnostics(h - eps * dh, u - eps * du)[1]
+    dE = (ep - em) / (2 * eps)
+    # scale: the rate at which either energy part alone changes
+    _, Ek = o.diagnostics(h, u + eps * du)
+    _, E0 = o.diagnostics(h, u)
+    assert abs(dE) < 1e-6 * abs((Ek - E0) / eps)
+    mp, _ = o.diagnostics(h + eps * dh, u)
+    m0, _ = o.diagnostics(h, u)
+    assert abs(mp - m0) < 1e-12 * m0

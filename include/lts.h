@@ -1,0 +1,179 @@
+/*
+ * liblts — LTS3 local time stepping for the TRiSK shallow water equations on
+ * Voronoi C-grid meshes, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Capodaglio & Petersen, "Local time stepping for the shallow water
+ * equations in MPAS" (arXiv 2106.07154): Algorithm 2.2 (LTS3, with LTS2 as its
+ * second-order branch) over the discrete system of eq:sweTimeStepping, whose
+ * right-hand side is the TRiSK discretisation of Appendix B.
+ *
+ * Conventions
+ *   - Every call returns lts_status (0 = LTS_OK, < 0 = error); the message of
+ *     the last error is available from lts_last_error().  A context is not
+ *     thread-safe: calls on one context must not overlap.
+ *   - Host arrays passed in are owned by the caller and copied during the call.
+ *     Device buffers are owned by the context and freed by lts_destroy().
+ *   - Indices are 0-based int32 in the caller's numbering; unused slots of
+ *     per-cell tables hold -1.  Layout is row-major: edges_on_cell[i*max_edges+j],
+ *     cells_on_edge[2*e+s], edges_on_vertex[3*v+k].
+ *   - Orientation: n_e points from cells_on_edge[e][0] to cells_on_edge[e][1]
+ *     (n_{e,c0} = +1, n_{e,c1} = -1, the sign correction of Appendix B);
+ *     t_e = k x n_e points from vertices_on_edge[e][0] to vertices_on_edge[e][1]
+ *     (t_{e,v1} = +1).  edges_on_cell lists a cell's edges counter-clockwise;
+ *     vertices_on_cell[i][j] is the vertex shared by edges_on_cell[i][j] and
+ *     edges_on_cell[i][j+1]; cells_on_cell[i][j] is the cell across
+ *     edges_on_cell[i][j].  Any flip of n_e (with u_e negated) is equivalent.
+ *   - State: thickness h at cells, normal velocity u at edges, always passed as
+ *     double on the host; on the device the context keeps it in its precision
+ *     (LTS_FP64 or LTS_FP32), permuted so every LTS region is a contiguous range.
+ *   - All work is enqueued on the context's HIP stream.  Calls that return host
+ *     data (lts_diagnostics, lts_get_state, lts_get_regions, lts_eval_rhs)
+ *     synchronise that stream; lts_step and lts_step_rk3 do not.
+ */
+#ifndef LTS_H
+#define LTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LTS_OK = 0,
+    LTS_EINVAL = -1,     /* bad argument (NULL pointer, M < 1, dt <= 0, ...)   */
+    LTS_EMESH = -2,      /* inconsistent mesh connectivity or geometry         */
+    LTS_ELABEL = -3,     /* unusable LTS regions (no fine cell, all fine, ...) */
+    LTS_ENONFINITE = -4, /* a step produced Inf/NaN; state invalid until init  */
+    LTS_EDEVICE = -5,    /* HIP runtime error                                  */
+    LTS_ESTATE = -6,     /* call out of order (no mesh, no state)              */
+    LTS_ENOMEM = -7      /* device or host allocation failed                   */
+} lts_status;
+
+typedef enum { LTS_FP64 = 0, LTS_FP32 = 1 } lts_precision;
+
+/* Region labels, eq:indexSetsCells / eq:indexSetsEdges. */
+typedef enum { LTS_C = 0, LTS_I2 = 1, LTS_I1 = 2, LTS_F = 3 } lts_region;
+
+/* Largest number of edges a cell may have. */
+#define LTS_MAX_EDGES 10
+
+typedef struct lts_ctx lts_ctx;
+
+/* MPAS-style mesh (Appendix B sets EC, EV, CE, VE; EE is derived). */
+typedef struct {
+    int32_t n_cells, n_edges, n_vertices, max_edges;
+    const int32_t *n_edges_on_cell;      /* [n_cells]                          */
+    const int32_t *edges_on_cell;        /* [n_cells][max_edges], ccw          */
+    const int32_t *cells_on_cell;        /* [n_cells][max_edges]               */
+    const int32_t *vertices_on_cell;     /* [n_cells][max_edges]               */
+    const int32_t *cells_on_edge;        /* [n_edges][2]                       */
+    const int32_t *vertices_on_edge;     /* [n_edges][2]                       */
+    const int32_t *edges_on_vertex;      /* [n_vertices][3]                    */
+    const int32_t *cells_on_vertex;      /* [n_vertices][3]                    */
+    const double *kite_areas_on_vertex;  /* [n_vertices][3]: A_{i,v}, i = cells_on_vertex[v][k] */
+    const double *area_cell;             /* [n_cells]    A_i                   */
+    const double *area_triangle;         /* [n_vertices] A_v                   */
+    const double *dc_edge;               /* [n_edges]    d_e (cell-to-cell)    */
+    const double *dv_edge;               /* [n_edges]    l_e (primal edge)     */
+    const double *f_vertex;              /* [n_vertices] Coriolis parameter    */
+    const double *bottom;                /* [n_cells]    topography b_i        */
+    const double *cell_xyz;              /* [n_cells][3] or NULL: positions, used
+                                            only to order cells for locality     */
+} lts_mesh;
+
+typedef struct {
+    double t;             /* simulated time                                     */
+    double mass;          /* sum_i A_i h_i, FP64 on the device                  */
+    double energy;        /* sum_i A_i (h_i K_i + g (h_i^2/2 + h_i b_i)), FP64  */
+    double h_min, h_max, u_absmax;
+    int64_t n_nonfinite;  /* non-finite h or u values in the state              */
+    int64_t steps;        /* coarse steps (LTS) or steps (RK3) taken            */
+} lts_diag;
+
+/* Create a context on HIP device `device`, computing in `prec`.  hip_stream is
+   a hipStream_t to enqueue on (it must outlive the context) or NULL for a
+   context-owned stream. */
+lts_status lts_create(lts_ctx **out, int device, lts_precision prec, void *hip_stream);
+
+/* Validate and upload the mesh, label the LTS regions (F = cells with
+   fine_mask != 0; I1 = n_if1_rings breadth-first cell rings around F; I2 = the
+   next n_if2_rings; C = the rest; underlined F = the two fine rings nearest
+   I1; each edge takes the finest region of its two cells) and fold the TRiSK
+   coefficients, including the weights of eq:weights, from the kite areas.
+   LTS_EMESH on inconsistent connectivity, LTS_ELABEL on unusable regions.
+   Replaces any previous mesh and invalidates the state. */
+lts_status lts_upload_mesh(lts_ctx *ctx, const lts_mesh *mesh, const uint8_t *fine_mask,
+                           int n_if1_rings, int n_if2_rings, double gravity);
+
+/* Region labels in the caller's numbering (host arrays, any may be NULL). */
+lts_status lts_get_regions(lts_ctx *ctx, int8_t *cell_region, int8_t *edge_region,
+                           uint8_t *cell_fbar, uint8_t *edge_fbar);
+
+/* Set the state from host arrays h[n_cells], u[n_edges] (caller numbering). */
+lts_status lts_init_state(lts_ctx *ctx, const double *h, const double *u, double t0);
+
+/* Same from device arrays in the context precision (caller numbering); they
+   are read only during the call. */
+lts_status lts_init_state_device(lts_ctx *ctx, const void *d_h, const void *d_u, double t0);
+
+/* Advance n_steps coarse steps of LTS3 (Algorithm 2.2, order 3) with coarse
+   step dt_coarse and fine step dt_coarse/M.  Asynchronous.  LTS_EINVAL when
+   M < 1 or dt_coarse <= 0. */
+lts_status lts_step(lts_ctx *ctx, double dt_coarse, int M, int n_steps);
+
+/* Advance n_steps steps of global SSPRK3 (Algorithm 2.1) with step dt over the
+   whole mesh; an independent code path from lts_step. */
+lts_status lts_step_rk3(lts_ctx *ctx, double dt, int n_steps);
+
+/* Evaluate the right-hand side (H, U) of eq:sweTimeStepping at the given host
+   state (caller numbering) over the whole mesh.  Does not change the state. */
+lts_status lts_eval_rhs(lts_ctx *ctx, const double *h, const double *u,
+                        double *dh, double *du);
+
+/* FP64 diagnostics of the current state (synchronises).  Returns
+   LTS_ENONFINITE, sticky until the next init, when a step produced Inf/NaN. */
+lts_status lts_diagnostics(lts_ctx *ctx, lts_diag *out);
+
+/* Copy the state to host doubles (caller numbering; synchronises). */
+lts_status lts_get_state(lts_ctx *ctx, double *h, double *u);
+
+/* Copy the state to device arrays in the context precision (caller numbering). */
+lts_status lts_get_state_device(lts_ctx *ctx, void *d_h, void *d_u);
+
+/* Per-kernel timing: when enabled, steps launch without graphs and bracket each
+   kernel with HIP events; lts_kernel_stats reports, per kernel class, the
+   number of launches, total milliseconds and the algorithmic bytes moved (see
+   the library documentation for the byte model).  Classes: 0 vertex PV,
+   1 cell tendency, 2 edge tendency, 3 interface prediction, 4 interface
+   correction, 5 copies.  Returns the number of classes written. */
+lts_status lts_set_timing(lts_ctx *ctx, int enable);
+int lts_kernel_stats(lts_ctx *ctx, int max_classes, int64_t *launches, double *ms,
+                     double *bytes);
+
+/* Element counts of the LTS regions after upload: cells[4] and edges[4] in
+   lts_region order (C, I2, I1, F), fbar[2] = underlined-F cells, edges. */
+lts_status lts_region_counts(lts_ctx *ctx, int64_t *cells, int64_t *edges, int64_t *fbar);
+
+/* Host-only planning, no device needed: validate `mesh`, label the regions
+   and compute the device ordering exactly as lts_upload_mesh does.  Outputs
+   (any may be NULL): region labels and underlined-F flags in caller numbering;
+   cell/edge/vertex order (position -> caller index); ranges[54] = 8 cell class
+   starts (F minus underlined F, F2, F1, I1, I2, C1, rest of C, end), 6 edge
+   class starts (F minus underlined F, underlined F, I1, I2, C, end), then for
+   each of the 5 pass kinds (full mesh, Step 1, Step 2, Step 3, Step 4) the
+   cell-kernel range, vertex range, target cells and target edges (8 ints).
+   On error the message goes to errbuf (errlen bytes, may be NULL). */
+lts_status lts_plan(const lts_mesh *mesh, const uint8_t *fine_mask, int n_if1_rings,
+                    int n_if2_rings, int8_t *cell_region, int8_t *edge_region,
+                    uint8_t *cell_fbar, uint8_t *edge_fbar, int32_t *cell_order,
+                    int32_t *edge_order, int32_t *vertex_order, int32_t *ranges,
+                    char *errbuf, int errlen);
+
+const char *lts_last_error(const lts_ctx *ctx);
+void lts_destroy(lts_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1204 @@
+// Host runtime of liblts: the C ABI declared in include/lts.h.
+//
+// Upload: validate the mesh, label the LTS regions (eq:indexSetsCells,
+// eq:index_sets_cells, eq:indexSetsEdges), permute cells, edges and vertices so
+// that every evaluation set of Algorithm 2.2 is a contiguous range, fold the
+// TRiSK coefficients (App. B) into per-cell slot tables, copy to the device.
+//
+// Cell order: [F minus underlined F | F2 | F1 | I1 | I2 | C1 | rest of C], where
+// F1 are fine cells next to I1, F2 the fine cells next to F1, C1 the coarse
+// cells next to I2.  Edge order: [edges of F minus underlined F cells |
+// underlined-F edges | I1 | I2 | C].  Vertex order: by the smallest position of
+// their three cells.  Within a class cells follow a Morton curve of their
+// positions when given (input order otherwise); edges and vertices follow
+// their cells.
+//
+// Step: one coarse LTS3 step is a fixed sequence of right-hand-side passes
+// (vertex, cell and edge kernels over the ranges of that pass) with the stage
+// arithmetic fused into the cell and edge kernels, captured once into a
+// hipGraph per (M, dt) and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lts_internal.h"
+
+using namespace lts;
+
+namespace {
+
+enum PassKind { P_FULL = 0, P_STEP1, P_STEP2, P_STEP3, P_STEP4, P_N };
+
+struct PassPlan {
+    int c_lo = 0, c_hi = 0;    // cell kernel range (targets plus cells of target edges)
+    int v_lo = 0, v_hi = 0;    // vertex kernel range
+    int ct_lo = 0, ct_hi = 0;  // target cells
+    int et_lo = 0, et_hi = 0;  // target edges
+    // algorithmic bytes of the gathers, per element type (counts of unique
+    // elements touched), filled at upload
+    long v_uniq_u = 0, v_uniq_h = 0;
+    long c_uniq_h = 0, c_uniq_u = 0, c_uniq_q = 0, c_slots = 0;
+};
+
+struct TimedLaunch {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct ImplBase {
+    virtual ~ImplBase() {}
+};
+
+}  // namespace
+
+struct lts_ctx {
+    int device = 0;
+    lts_precision prec = LTS_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    bool has_mesh = false, has_state = false, nonfinite = false;
+    int nC = 0, nE = 0, nV = 0, maxE = 0;
+    double g = 9.81;
+    std::vector<int32_t> cperm, cinv, eperm, einv, vperm, vinv;  // perm: new->old, inv: old->new
+    std::vector<int8_t> creg, ereg;                              // caller numbering
+    std::vector<uint8_t> cfbar, efbar;
+    int cb[8] = {0};  // cell class starts: Fint F2 F1 I1 I2 C1 Crest end
+    int eb[6] = {0};  // edge class starts: Fint Fbar I1 I2 C end
+    PassPlan plan[P_N];
+
+    // device memory (typed by prec); all owned
+    std::vector<void*> allocs;
+    void* dm = nullptr;  // DevMesh<T>*
+    void *Ah = nullptr, *Au = nullptr, *Bh = nullptr, *Bu = nullptr, *Ch = nullptr, *Cu = nullptr;
+    void *x0h = nullptr, *x1h = nullptr, *x2h = nullptr, *x0u = nullptr, *x1u = nullptr,
+         *x2u = nullptr;
+    void *acch = nullptr, *accu = nullptr, *zs = nullptr, *q = nullptr;
+    int* flag = nullptr;
+    double *dpart = nullptr, *dout = nullptr;
+
+    double t = 0.0;
+    int64_t steps = 0;
+
+    // graph cache for one coarse step
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_kind = -1, g_M = 0;
+    double g_dt = 0.0;
+
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> evpool;
+    int64_t st_launch[KC_N] = {0};
+    double st_ms[KC_N] = {0}, st_bytes[KC_N] = {0};
+};
+
+namespace {
+
+lts_status fail(lts_ctx* c, lts_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, LTS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t tsize(const lts_ctx* c) { return c->prec == LTS_FP64 ? 8 : 4; }
+
+lts_status dalloc(lts_ctx* c, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(c, LTS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->allocs.push_back(*p);
+    return LTS_OK;
+}
+
+void free_device(lts_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_kind = -1;
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->dm) {
+        if (c->prec == LTS_FP64) delete static_cast<DevMesh<double>*>(c->dm);
+        else delete static_cast<DevMesh<float>*>(c->dm);
+    }
+    c->dm = nullptr;
+}
+
+// ---------------------------------------------------------------- validation
+lts_status validate(lts_ctx* c, const lts_mesh* m) {
+    const int nC = m->n_cells, nE = m->n_edges, nV = m->n_vertices, mx = m->max_edges;
+    if (nC < 3 || nE < 3 || nV < 3 || mx < 3)
+        return fail(c, LTS_EMESH, "mesh sizes too small");
+    if (mx > LTS_MAX_EDGES) return fail(c, LTS_EMESH, "max_edges exceeds LTS_MAX_EDGES");
+    const void* req[] = {m->n_edges_on_cell, m->edges_on_cell, m->cells_on_cell,
+                         m->vertices_on_cell, m->cells_on_edge, m->vertices_on_edge,
+                         m->edges_on_vertex, m->cells_on_vertex, m->kite_areas_on_vertex,
+                         m->area_cell, m->area_triangle, m->dc_edge, m->dv_edge,
+                         m->f_vertex, m->bottom};
+    for (const void* p : req)
+        if (!p) return fail(c, LTS_EINVAL, "NULL mesh array");
+    std::vector<int> edge_seen(nE, 0);
+    for (int i = 0; i < nC; ++i) {
+        const int n = m->n_edges_on_cell[i];
+        if (n < 3 || n > mx) return fail(c, LTS_EMESH, "n_edges_on_cell out of range at cell " + std::to_string(i));
+        if (!(m->area_cell[i] > 0)) return fail(c, LTS_EMESH, "non-positive area_cell");
+        for (int j = 0; j < n; ++j) {
+            const int e = m->edges_on_cell[(size_t)i * mx + j];
+            const int nb = m->cells_on_cell[(size_t)i * mx + j];
+            const int v = m->vertices_on_cell[(size_t)i * mx + j];
+            if (e < 0 || e >= nE || nb < 0 || nb >= nC || v < 0 || v >= nV)
+                return fail(c, LTS_EMESH, "index out of range at cell " + std::to_string(i));
+            const int c0 = m->cells_on_edge[2 * e], c1 = m->cells_on_edge[2 * e + 1];
+            if (!((c0 == i && c1 == nb) || (c1 == i && c0 == nb)))
+                return fail(c, LTS_EMESH, "edge/cell mismatch at cell " + std::to_string(i));
+            const int en = m->edges_on_cell[(size_t)i * mx + (j + 1) % n];
+            if (en < 0 || en >= nE) return fail(c, LTS_EMESH, "index out of range");
+            const int* ve = m->vertices_on_edge + 2 * e;
+            const int* vn = m->vertices_on_edge + 2 * en;
+            if (!((ve[0] == v || ve[1] == v) && (vn[0] == v || vn[1] == v)))
+                return fail(c, LTS_EMESH, "vertex slot not shared by its edges at cell " + std::to_string(i));
+            edge_seen[e]++;
+        }
+    }
+    for (int e = 0; e < nE; ++e) {
+        if (edge_seen[e] != 2) return fail(c, LTS_EMESH, "edge not on exactly two cells: " + std::to_string(e));
+        if (!(m->dc_edge[e] > 0) || !(m->dv_edge[e] > 0))
+            return fail(c, LTS_EMESH, "non-positive edge length");
+        for (int s = 0; s < 2; ++s) {
+            const int v = m->vertices_on_edge[2 * e + s];
+            if (v < 0 || v >= nV) return fail(c, LTS_EMESH, "vertex index out of range");
+        }
+    }
+    for (int v = 0; v < nV; ++v) {
+        if (!(m->area_triangle[v] > 0)) return fail(c, LTS_EMESH, "non-positive area_triangle");
+        for (int k = 0; k < 3; ++k) {
+            const int e = m->edges_on_vertex[3 * v + k];
+            const int ci = m->cells_on_vertex[3 * v + k];
+            if (e < 0 || e >= nE || ci < 0 || ci >= nC)
+                return fail(c, LTS_EMESH, "vertex degree is not 3 or index out of range");
+            if (m->vertices_on_edge[2 * e] != v && m->vertices_on_edge[2 * e + 1] != v)
+                return fail(c, LTS_EMESH, "edges_on_vertex inconsistent at vertex " + std::to_string(v));
+            bool found = false;
+            for (int j = 0; j < m->n_edges_on_cell[ci]; ++j)
+                if (m->vertices_on_cell[(size_t)ci * mx + j] == v) found = true;
+            if (!found) return fail(c, LTS_EMESH, "cells_on_vertex inconsistent at vertex " + std::to_string(v));
+            if (!(m->kite_areas_on_vertex[3 * v + k] > 0))
+                return fail(c, LTS_EMESH, "non-positive kite area");
+        }
+    }
+    return LTS_OK;
+}
+
+// ---------------------------------------------------------------- regions
+// Breadth-first rings around the fine set (eq:indexSetsCells with n1 and n2
+// rings), F1/F2 (eq:index_sets_cells), edges to the finest adjacent region.
+lts_status label_regions(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1, int n2,
+                         std::vector<int>& cls, std::vector<int>& ecls) {
+    const int nC = m->n_cells, nE = m->n_edges, mx = m->max_edges;
+    if (n1 < 1 || n2 < 1) return fail(c, LTS_ELABEL, "interface rings must be >= 1");
+    std::vector<int> ring(nC, -1), frontier, next;
+    for (int i = 0; i < nC; ++i)
+        if (fine[i]) { ring[i] = 0; frontier.push_back(i); }
+    if (frontier.empty()) return fail(c, LTS_ELABEL, "empty fine region");
+    if ((int)frontier.size() == nC) return fail(c, LTS_ELABEL, "every cell is fine");
+    for (int r = 1; r <= n1 + n2; ++r) {
+        next.clear();
+        for (int i : frontier)
+            for (int j = 0; j < m->n_edges_on_cell[i]; ++j) {
+                const int nb = m->cells_on_cell[(size_t)i * mx + j];
+                if (ring[nb] == -1) { ring[nb] = r; next.push_back(nb); }
+            }
+        frontier.swap(next);
+    }
+    c->creg.assign(nC, LTS_C);
+    for (int i = 0; i < nC; ++i) {
+        if (ring[i] == 0) c->creg[i] = LTS_F;
+        else if (ring[i] >= 1 && ring[i] <= n1) c->creg[i] = LTS_I1;
+        else if (ring[i] > n1) c->creg[i] = LTS_I2;
+    }
+    // classes: 0 Fint, 1 F2, 2 F1, 3 I1, 4 I2, 5 C1, 6 Crest
+    cls.assign(nC, 6);
+    for (int i = 0; i < nC; ++i) {
+        if (c->creg[i] == LTS_I1) cls[i] = 3;
+        else if (c->creg[i] == LTS_I2) cls[i] = 4;
+        else if (c->creg[i] == LTS_F) cls[i] = 0;
+    }
+    auto touches = [&](int i, auto pred) {
+        for (int j = 0; j < m->n_edges_on_cell[i]; ++j)
+            if (pred(m->cells_on_cell[(size_t)i * mx + j])) return true;
+        return false;
+    };
+    for (int i = 0; i < nC; ++i)
+        if (c->creg[i] == LTS_F && touches(i, [&](int k) { return c->creg[k] == LTS_I1; })) cls[i] = 2;
+    for (int i = 0; i < nC; ++i)
+        if (cls[i] == 0 && touches(i, [&](int k) { return cls[k] == 2; })) cls[i] = 1;
+    for (int i = 0; i < nC; ++i)
+        if (c->creg[i] == LTS_C && touches(i, [&](int k) { return c->creg[k] == LTS_I2; })) cls[i] = 5;
+    c->cfbar.assign(nC, 0);
+    for (int i = 0; i < nC; ++i) c->cfbar[i] = (cls[i] == 1 || cls[i] == 2) ? 1 : 0;
+    // edges: 0 Fint, 1 Fbar, 2 I1, 3 I2, 4 C
+    ecls.assign(nE, 4);
+    c->ereg.assign(nE, LTS_C);
+    c->efbar.assign(nE, 0);
+    for (int e = 0; e < nE; ++e) {
+        const int a = m->cells_on_edge[2 * e], b = m->cells_on_edge[2 * e + 1];
+        const int r = std::max(c->creg[a], c->creg[b]);
+        c->ereg[e] = (int8_t)r;
+        const bool fint = cls[a] == 0 || cls[b] == 0;
+        if (r == LTS_F) {
+            ecls[e] = fint ? 0 : 1;
+            c->efbar[e] = fint ? 0 : 1;
+        } else if (r == LTS_I1) ecls[e] = 2;
+        else if (r == LTS_I2) ecls[e] = 3;
+    }
+    return LTS_OK;
+}
+
+uint64_t spread3(uint64_t x) {
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+// ---------------------------------------------------------------- typed setup
+template <typename T>
+std::vector<T> conv(const std::vector<double>& v) {
+    return std::vector<T>(v.begin(), v.end());
+}
+
+template <typename T>
+lts_status upload_vec(lts_ctx* c, const T** dst, const std::vector<T>& v) {
+    void* p = nullptr;
+    lts_status s = dalloc(c, &p, v.size() * sizeof(T));
+    if (s) return s;
+    HIPCHK(c, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *dst = static_cast<const T*>(p);
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status build_device(lts_ctx* c, const lts_mesh* m) {
+    const int nC = c->nC, nE = c->nE, nV = c->nV, mx = c->maxE;
+    const int* cinv = c->cinv.data();
+    const int* einv = c->einv.data();
+    const int* vinv = c->vinv.data();
+    std::vector<int32_t> nEoC(nC), eoc((size_t)mx * nC, 0), coc((size_t)mx * nC, 0),
+        voc((size_t)mx * nC, 0);
+    std::vector<double> nl((size_t)mx * nC, 0), nd((size_t)mx * nC, 0), kc((size_t)mx * nC, 0),
+        kf((size_t)mx * nC, 0), area(nC), bot(nC);
+    for (int ni = 0; ni < nC; ++ni) {
+        const int i = c->cperm[ni];
+        const int n = m->n_edges_on_cell[i];
+        nEoC[ni] = n;
+        area[ni] = m->area_cell[i];
+        bot[ni] = m->bottom[i];
+        for (int j = 0; j < n; ++j) {
+            const size_t o = (size_t)j * nC + ni;
+            const int e = m->edges_on_cell[(size_t)i * m->max_edges + j];
+            const int v = m->vertices_on_cell[(size_t)i * m->max_edges + j];
+            eoc[o] = einv[e];
+            coc[o] = cinv[m->cells_on_cell[(size_t)i * m->max_edges + j]];
+            voc[o] = vinv[v];
+            const double sgn = m->cells_on_edge[2 * e] == i ? 1.0 : -1.0;  // n_{e,i}
+            nl[o] = sgn * m->dv_edge[e];
+            nd[o] = sgn / m->dc_edge[e];
+            kc[o] = m->dv_edge[e] * m->dc_edge[e] / (4.0 * m->area_cell[i]);
+            double kite = 0.0;
+            for (int k = 0; k < 3; ++k)
+                if (m->cells_on_vertex[3 * v + k] == i) kite = m->kite_areas_on_vertex[3 * v + k];
+            kf[o] = kite / m->area_cell[i];
+        }
+    }
+    std::vector<int32_t> eov((size_t)3 * nV), cov((size_t)3 * nV);
+    std::vector<double> tdc((size_t)3 * nV), kite((size_t)3 * nV), fA(nV);
+    for (int nv = 0; nv < nV; ++nv) {
+        const int v = c->vperm[nv];
+        fA[nv] = m->f_vertex[v] * m->area_triangle[v];
+        for (int k = 0; k < 3; ++k) {
+            const size_t o = (size_t)k * nV + nv;
+            const int e = m->edges_on_vertex[3 * v + k];
+            eov[o] = einv[e];
+            const double tsg = m->vertices_on_edge[2 * e + 1] == v ? 1.0 : -1.0;  // t_{e,v}
+            tdc[o] = tsg * m->dc_edge[e];
+            cov[o] = cinv[m->cells_on_vertex[3 * v + k]];
+            kite[o] = m->kite_areas_on_vertex[3 * v + k];
+        }
+    }
+    auto* dm = new DevMesh<T>();
+    c->dm = dm;
+    dm->nC = nC;
+    dm->nE = nE;
+    dm->nV = nV;
+    dm->maxE = mx;
+    lts_status s;
+    if ((s = upload_vec<int32_t>(c, &dm->nEoC, nEoC))) return s;
+    if ((s = upload_vec<int32_t>(c, &dm->eoc, eoc))) return s;
+    if ((s = upload_vec<int32_t>(c, &dm->coc, coc))) return s;
+    if ((s = upload_vec<int32_t>(c, &dm->voc, voc))) return s;
+    if ((s = upload_vec<T>(c, &dm->nl, conv<T>(nl)))) return s;
+    if ((s = upload_vec<T>(c, &dm->nd, conv<T>(nd)))) return s;
+    if ((s = upload_vec<T>(c, &dm->kc, conv<T>(kc)))) return s;
+    if ((s = upload_vec<T>(c, &dm->kf, conv<T>(kf)))) return s;
+    if ((s = upload_vec<T>(c, &dm->area, conv<T>(area)))) return s;
+    if ((s = upload_vec<T>(c, &dm->bot, conv<T>(bot)))) return s;
+    if ((s = upload_vec<int32_t>(c, &dm->eov, eov))) return s;
+    if ((s = upload_vec<int32_t>(c, &dm->cov, cov))) return s;
+    if ((s = upload_vec<T>(c, &dm->tdc, conv<T>(tdc)))) return s;
+    if ((s = upload_vec<T>(c, &dm->kite, conv<T>(kite)))) return s;
+    if ((s = upload_vec<T>(c, &dm->fA, conv<T>(fA)))) return s;
+
+    const size_t ts = sizeof(T);
+    const int nI1c = c->cb[4] - c->cb[3], nI1e = c->eb[3] - c->eb[2];
+    const int nIc = c->cb[5] - c->cb[3], nIe = c->eb[4] - c->eb[2];
+    void** bufs[] = {&c->Ah, &c->Bh, &c->Ch};
+    for (void** b : bufs) if ((s = dalloc(c, b, nC * ts))) return s;
+    void** ubufs[] = {&c->Au, &c->Bu, &c->Cu};
+    for (void** b : ubufs) if ((s = dalloc(c, b, nE * ts))) return s;
+    if ((s = dalloc(c, &c->x0h, nI1c * ts)) || (s = dalloc(c, &c->x1h, nI1c * ts)) ||
+        (s = dalloc(c, &c->x2h, nI1c * ts)) || (s = dalloc(c, &c->x0u, nI1e * ts)) ||
+        (s = dalloc(c, &c->x1u, nI1e * ts)) || (s = dalloc(c, &c->x2u, nI1e * ts)) ||
+        (s = dalloc(c, &c->acch, nIc * ts)) || (s = dalloc(c, &c->accu, nIe * ts)) ||
+        (s = dalloc(c, &c->zs, 2 * (size_t)nE * ts)) || (s = dalloc(c, &c->q, nV * ts)))
+        return s;
+    void* fp = nullptr;
+    if ((s = dalloc(c, &fp, 64))) return s;
+    c->flag = static_cast<int*>(fp);
+    const int nblk = diag_blocks(nC) + diag_blocks(nE);
+    void* pp = nullptr;
+    if ((s = dalloc(c, &pp, (size_t)nblk * 8 * sizeof(double)))) return s;
+    c->dpart = static_cast<double*>(pp);
+    if ((s = dalloc(c, &pp, 8 * sizeof(double)))) return s;
+    c->dout = static_cast<double*>(pp);
+    // zero every state-sized buffer so ranges that read beyond the evaluated
+    // set (never used) see finite numbers
+    for (void* b : {c->Ah, c->Bh, c->Ch}) HIPCHK(c, hipMemset(b, 0, nC * ts));
+    for (void* b : {c->Au, c->Bu, c->Cu}) HIPCHK(c, hipMemset(b, 0, nE * ts));
+    HIPCHK(c, hipMemset(c->zs, 0, 2 * (size_t)nE * ts));
+    HIPCHK(c, hipMemset(c->q, 0, nV * ts));
+    HIPCHK(c, hipMemset(c->flag, 0, 64));
+    HIPCHK(c, hipDeviceSynchronize());
+    return LTS_OK;
+}
+
+// ---------------------------------------------------------------- plans
+void make_plans(lts_ctx* c, const lts_mesh* m) {
+    const int nC = c->nC, nE = c->nE;
+    const int* cb = c->cb;
+    const int* eb = c->eb;
+    struct T4 { int ct_lo, ct_hi, et_lo, et_hi; };
+    const T4 targets[P_N] = {
+        {0, nC, 0, nE},            // FULL
+        {cb[1], nC, eb[1], nE},    // STEP1: underlined F, I, C
+        {cb[3], nC, eb[2], nE},    // STEP2: I, C
+        {0, cb[5], 0, eb[4]},      // STEP3: F, I (fine edges, I edges)
+        {cb[5], nC, eb[4], nE},    // STEP4: C
+    };
+    // new-numbering connectivity needed for coverage
+    for (int p = 0; p < P_N; ++p) {
+        PassPlan& P = c->plan[p];
+        P.ct_lo = targets[p].ct_lo;
+        P.ct_hi = targets[p].ct_hi;
+        P.et_lo = targets[p].et_lo;
+        P.et_hi = targets[p].et_hi;
+        int lo = P.ct_lo, hi = P.ct_hi;
+        if (P.ct_hi <= P.ct_lo) { lo = nC; hi = 0; }
+        for (int ne = P.et_lo; ne < P.et_hi; ++ne) {
+            const int e = c->eperm[ne];
+            for (int s = 0; s < 2; ++s) {
+                const int ci = c->cinv[m->cells_on_edge[2 * e + s]];
+                lo = std::min(lo, ci);
+                hi = std::max(hi, ci + 1);
+            }
+        }
+        if (hi <= lo) { lo = hi = 0; }
+        P.c_lo = lo;
+        P.c_hi = hi;
+        int vlo = c->nV, vhi = 0;
+        std::vector<char> useu(nE, 0), useh(nC, 0), useq(c->nV, 0);
+        long slots = 0;
+        for (int ni = lo; ni < hi; ++ni) {
+            const int i = c->cperm[ni];
+            useh[ni] = 1;
+            for (int j = 0; j < m->n_edges_on_cell[i]; ++j) {
+                const int v = c->vinv[m->vertices_on_cell[(size_t)i * m->max_edges + j]];
+                vlo = std::min(vlo, v);
+                vhi = std::max(vhi, v + 1);
+                useq[v] = 1;
+                useu[c->einv[m->edges_on_cell[(size_t)i * m->max_edges + j]]] = 1;
+                useh[c->cinv[m->cells_on_cell[(size_t)i * m->max_edges + j]]] = 1;
+                ++slots;
+            }
+        }
+        if (vhi <= vlo) { vlo = vhi = 0; }
+        P.v_lo = vlo;
+        P.v_hi = vhi;
+        P.c_uniq_h = std::count(useh.begin(), useh.end(), 1);
+        P.c_uniq_u = std::count(useu.begin(), useu.end(), 1);
+        P.c_uniq_q = std::count(useq.begin(), useq.end(), 1);
+        P.c_slots = slots;
+        std::vector<char> vu(nE, 0), vh(nC, 0);
+        for (int nv = vlo; nv < vhi; ++nv) {
+            const int v = c->vperm[nv];
+            for (int k = 0; k < 3; ++k) {
+                vu[c->einv[m->edges_on_vertex[3 * v + k]]] = 1;
+                vh[c->cinv[m->cells_on_vertex[3 * v + k]]] = 1;
+            }
+        }
+        P.v_uniq_u = std::count(vu.begin(), vu.end(), 1);
+        P.v_uniq_h = std::count(vh.begin(), vh.end(), 1);
+    }
+}
+
+// ---------------------------------------------------------------- launches
+template <typename T>
+struct Run {
+    lts_ctx* c;
+    const DevMesh<T>& dm;
+    hipStream_t s;
+    bool timed;
+
+    lts_status begin(hipEvent_t* ev) {
+        if (!timed) return LTS_OK;
+        if (c->evpool.size() < 2) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->evpool.push_back(e);
+            }
+        }
+        *ev = c->evpool.back();
+        c->evpool.pop_back();
+        HIPCHK(c, hipEventRecord(*ev, s));
+        return LTS_OK;
+    }
+    lts_status end(int cls, hipEvent_t a, double bytes) {
+        if (!timed) return LTS_OK;
+        if (c->evpool.empty()) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->evpool.push_back(e);
+        }
+        hipEvent_t b = c->evpool.back();
+        c->evpool.pop_back();
+        HIPCHK(c, hipEventRecord(b, s));
+        c->pending.push_back({cls, a, b, bytes});
+        return LTS_OK;
+    }
+
+    static double seg_bytes(const Seg<T>& g) {
+        if (!g.mode || g.hi <= g.lo) return 0.0;
+        const double n = g.hi - g.lo;
+        if (g.mode == 1) return n * sizeof(T) * (1 + (g.xold ? 1 : 0) + (g.xcur ? 1 : 0));
+        return n * sizeof(T) * (g.first ? 1 : 2);
+    }
+
+    // One right-hand-side pass of kind p over state (h, u) with epilogues.
+    lts_status pass(int p, const T* h, const T* u, const Seg<T>& cs0, const Seg<T>& cs1,
+                    const Seg<T>& es0, const Seg<T>& es1) {
+        const PassPlan& P = c->plan[p];
+        T* q = static_cast<T*>(c->q);
+        T* zs = static_cast<T*>(c->zs);
+        const double ts = sizeof(T);
+        hipEvent_t ev = nullptr;
+        lts_status st;
+        // vertex PV
+        if ((st = begin(&ev))) return st;
+        HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s));
+        const double nv = P.v_hi - P.v_lo;
+        if ((st = end(KC_VERTEX, ev, nv * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts)))
+            return st;
+        // cell tendency + partials
+        if ((st = begin(&ev))) return st;
+        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag, s));
+        const double ncell = P.c_hi - P.c_lo;
+        const double cb = ncell * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
+                          (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(cs0) +
+                          seg_bytes(cs1);
+        if ((st = end(KC_CELL, ev, cb))) return st;
+        // edge tendency
+        if ((st = begin(&ev))) return st;
+        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, c->flag, s));
+        const double eb = (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(es0) + seg_bytes(es1);
+        if ((st = end(KC_EDGE, ev, eb))) return st;
+        return LTS_OK;
+    }
+
+    static Seg<T> upd(int lo, int hi, T* out, const T* xold, double a_old, const T* xcur,
+                      double a_cur, double a_dt) {
+        Seg<T> g;
+        g.lo = lo;
+        g.hi = hi;
+        g.mode = hi > lo ? 1 : 0;
+        g.out = out;
+        g.xold = xold;
+        g.a_old = (T)a_old;
+        g.xcur = xcur;
+        g.a_cur = (T)a_cur;
+        g.a_dt = (T)a_dt;
+        return g;
+    }
+    static Seg<T> accum(int lo, int hi, T* acc, double theta, bool first) {
+        Seg<T> g;
+        g.lo = lo;
+        g.hi = hi;
+        g.mode = hi > lo ? 2 : 0;
+        g.acc = acc;
+        g.theta = (T)theta;
+        g.first = first ? 1 : 0;
+        return g;
+    }
+
+    lts_status predict(T* xh, T* xu, const double cf[3]) {
+        hipEvent_t ev = nullptr;
+        lts_status st;
+        if ((st = begin(&ev))) return st;
+        const int nh = c->cb[4] - c->cb[3], nu = c->eb[3] - c->eb[2];
+        HIPCHK(c, launch_predict<T>(xh, (T*)c->x0h, (T*)c->x1h, (T*)c->x2h, c->cb[3], nh, xu,
+                                    (T*)c->x0u, (T*)c->x1u, (T*)c->x2u, c->eb[2], nu, cf[0],
+                                    cf[1], cf[2], s));
+        return end(KC_PREDICT, ev, (nh + nu) * 4.0 * sizeof(T));
+    }
+    lts_status copy_i1(T* dh, const T* sh, T* du, const T* su) {
+        hipEvent_t ev = nullptr;
+        lts_status st;
+        if ((st = begin(&ev))) return st;
+        const int nh = c->cb[4] - c->cb[3], nu = c->eb[3] - c->eb[2];
+        HIPCHK(c, launch_copy<T>(dh, sh, c->cb[3], nh, du, su, c->eb[2], nu, s));
+        return end(KC_COPY, ev, (nh + nu) * 2.0 * sizeof(T));
+    }
+
+    // Algorithm 2.2, order 3: one coarse step on the state in A.
+    lts_status lts3_step(double dt, int M) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu;
+        const int* cb = c->cb;
+        const int* eb = c->eb;
+        const int nC = c->nC, nE = c->nE;
+        const double delta = dt / M;
+        const Seg<T> none;
+        lts_status st;
+        // Step 1: first stage with dt on underlined F, I1, I2, C
+        if ((st = pass(P_STEP1, Ah, Au, upd(cb[1], nC, Bh, nullptr, 0, Ah, 1, dt), none,
+                       upd(eb[1], nE, Bu, nullptr, 0, Au, 1, dt), none)))
+            return st;
+        if ((st = copy_i1((T*)c->x0h, Ah, (T*)c->x0u, Au))) return st;
+        if ((st = copy_i1((T*)c->x1h, Bh, (T*)c->x1u, Bu))) return st;
+        // Step 2: second stage with dt on I1, I2, C
+        if ((st = pass(P_STEP2, Bh, Bu, upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), none,
+                       upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), none)))
+            return st;
+        if ((st = copy_i1((T*)c->x2h, Ch, (T*)c->x2u, Cu))) return st;
+        // Step 3: M fine SSPRK3 substeps on F; I1 predicted, I accumulates
+        double cf[3];
+        for (int k = 0; k < M; ++k) {
+            // stage (old,k): A holds F at substep k, X0 on I2 and C
+            if (k > 0) {
+                predict_coeffs(0, k, M, cf);
+                if ((st = predict(Ah, Au, cf))) return st;
+            }
+            if ((st = pass(P_STEP3, Ah, Au, upd(0, cb[3], Bh, nullptr, 0, Ah, 1, delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, k == 0),
+                           upd(0, eb[2], Bu, nullptr, 0, Au, 1, delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, k == 0))))
+                return st;
+            // stage (1st,k): B holds stage-1 F, X1 on I2 and C
+            predict_coeffs(1, k, M, cf);
+            if ((st = predict(Bh, Bu, cf))) return st;
+            if ((st = pass(P_STEP3, Bh, Bu, upd(0, cb[3], Ch, Ah, 0.75, Bh, 0.25, 0.25 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, false),
+                           upd(0, eb[2], Cu, Au, 0.75, Bu, 0.25, 0.25 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, false))))
+                return st;
+            // stage (2nd,k): C holds stage-2 F, X2 on I2 and C; new F into A
+            predict_coeffs(2, k, M, cf);
+            if ((st = predict(Ch, Cu, cf))) return st;
+            if ((st = pass(P_STEP3, Ch, Cu,
+                           upd(0, cb[3], Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 2.0 / 3.0, false),
+                           upd(0, eb[2], Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 2.0 / 3.0, false))))
+                return st;
+        }
+        // Step 4: third stage with dt on C (reads X2 in C and I2 only)
+        if ((st = pass(P_STEP4, Ch, Cu,
+                       upd(cb[5], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
+                       upd(eb[4], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none)))
+            return st;
+        // Step 5: interface correction x = x_old + dt/M * acc on I1 u I2
+        hipEvent_t ev = nullptr;
+        if ((st = begin(&ev))) return st;
+        const int nIc = cb[5] - cb[3], nIe = eb[4] - eb[2];
+        HIPCHK(c, launch_correct<T>(Ah, (T*)c->x0h, (T*)c->acch, cb[3], nIc, cb[4] - cb[3], Au,
+                                    (T*)c->x0u, (T*)c->accu, eb[2], nIe, eb[3] - eb[2], delta,
+                                    s));
+        return end(KC_CORRECT, ev, (nIc + nIe) * 3.0 * sizeof(T));
+    }
+
+    // Algorithm 2.1, SSPRK3, over the whole mesh.
+    lts_status rk3_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        if ((st = pass(P_FULL, Ah, Au, upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), none,
+                       upd(0, nE, Bu, nullptr, 0, Au, 1, dt), none)))
+            return st;
+        if ((st = pass(P_FULL, Bh, Bu, upd(0, nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), none,
+                       upd(0, nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), none)))
+            return st;
+        return pass(P_FULL, Ch, Cu, upd(0, nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                    none, upd(0, nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none);
+    }
+
+    // Interface-1 prediction coefficients of Algorithm 2.2 (Steps 3.1.1,
+    // 3.2.1, 3.3.1), in FP64: (1 - a - a~, a - a~, 2 a~).
+    static void predict_coeffs(int stage, int k, int M, double out[3]) {
+        const double dk = k, dM = M;
+        double a, at;
+        if (stage == 0) {
+            a = dk / dM;
+            at = (dk * dk) / (dM * dM);
+        } else if (stage == 1) {
+            a = (dk + 1.0) / dM;
+            at = dk * (dk + 2.0) / (dM * dM);
+        } else {
+            a = (2.0 * dk + 1.0) / (2.0 * dM);
+            at = (2.0 * dk * dk + 2.0 * dk + 1.0) / (2.0 * dM * dM);
+        }
+        out[0] = 1.0 - a - at;
+        out[1] = a - at;
+        out[2] = 2.0 * at;
+    }
+};
+
+template <typename T>
+lts_status run_lts(lts_ctx* c, double dt, int M, int n) {
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    Run<T> r{c, dm, c->stream, c->timing};
+    if (c->timing) {
+        for (int i = 0; i < n; ++i) {
+            lts_status st = r.lts3_step(dt, M);
+            if (st) return st;
+        }
+        return LTS_OK;
+    }
+    if (!(c->gexec && c->g_kind == 0 && c->g_M == M && c->g_dt == dt)) {
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+        c->g_kind = -1;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        lts_status st = r.lts3_step(dt, M);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &gr);
+        if (st) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, LTS_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        c->graph = gr;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
+        c->g_kind = 0;
+        c->g_M = M;
+        c->g_dt = dt;
+    }
+    for (int i = 0; i < n; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status run_rk3(lts_ctx* c, double dt, int n) {
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    Run<T> r{c, dm, c->stream, c->timing};
+    if (c->timing) {
+        for (int i = 0; i < n; ++i) {
+            lts_status st = r.rk3_step(dt);
+            if (st) return st;
+        }
+        return LTS_OK;
+    }
+    if (!(c->gexec && c->g_kind == 1 && c->g_dt == dt)) {
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+        c->g_kind = -1;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        lts_status st = r.rk3_step(dt);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &gr);
+        if (st) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, LTS_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        c->graph = gr;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
+        c->g_kind = 1;
+        c->g_M = 0;
+        c->g_dt = dt;
+    }
+    for (int i = 0; i < n; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, double* du) {
+    const int nC = c->nC, nE = c->nE;
+    std::vector<T> hh(nC), uu(nE);
+    for (int ni = 0; ni < nC; ++ni) hh[ni] = (T)h[c->cperm[ni]];
+    for (int ne = 0; ne < nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
+    HIPCHK(c, hipMemcpyAsync(c->Bh, hh.data(), nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->Bu, uu.data(), nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    Run<T> r{c, dm, c->stream, false};
+    const Seg<T> none;
+    lts_status st = r.pass(P_FULL, (T*)c->Bh, (T*)c->Bu,
+                           Run<T>::upd(0, nC, (T*)c->Ch, nullptr, 0, nullptr, 0, 1.0), none,
+                           Run<T>::upd(0, nE, (T*)c->Cu, nullptr, 0, nullptr, 0, 1.0), none);
+    if (st) return st;
+    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ch, nC * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Cu, nE * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int ni = 0; ni < nC; ++ni) dh[c->cperm[ni]] = (double)hh[ni];
+    for (int ne = 0; ne < nE; ++ne) du[c->eperm[ne]] = (double)uu[ne];
+    // eval_rhs clobbers the stage buffers: force the next step to re-capture
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status set_state(lts_ctx* c, const double* h, const double* u) {
+    std::vector<T> hh(c->nC), uu(c->nE);
+    for (int ni = 0; ni < c->nC; ++ni) hh[ni] = (T)h[c->cperm[ni]];
+    for (int ne = 0; ne < c->nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
+    HIPCHK(c, hipMemcpyAsync(c->Ah, hh.data(), c->nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->Au, uu.data(), c->nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status get_state(lts_ctx* c, double* h, double* u) {
+    std::vector<T> hh(c->nC), uu(c->nE);
+    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ah, c->nC * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Au, c->nE * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h) for (int ni = 0; ni < c->nC; ++ni) h[c->cperm[ni]] = (double)hh[ni];
+    if (u) for (int ne = 0; ne < c->nE; ++ne) u[c->eperm[ne]] = (double)uu[ne];
+    return LTS_OK;
+}
+
+template <typename T>
+lts_status diagnostics(lts_ctx* c, double out[8]) {
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    HIPCHK(c, launch_diag<T>(dm, (T*)c->Ah, (T*)c->Au, c->g, c->dpart, diag_blocks(c->nC),
+                             diag_blocks(c->nE), c->dout, c->stream));
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(out, c->dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[6] = flag;
+    return LTS_OK;
+}
+
+lts_status ready(lts_ctx* c, bool need_state) {
+    if (!c) return LTS_EINVAL;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return fail(c, LTS_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    if (!c->has_mesh) return fail(c, LTS_ESTATE, "no mesh uploaded");
+    if (need_state && !c->has_state) return fail(c, LTS_ESTATE, "no state initialised");
+    return LTS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+lts_status lts_create(lts_ctx** out, int device, lts_precision prec, void* hip_stream) {
+    if (!out) return LTS_EINVAL;
+    *out = nullptr;
+    if (prec != LTS_FP64 && prec != LTS_FP32) return LTS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LTS_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LTS_EDEVICE;
+    lts_ctx* c = new lts_ctx();
+    c->device = device;
+    c->prec = prec;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return LTS_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return LTS_OK;
+}
+
+void lts_destroy(lts_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    free_device(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* lts_last_error(const lts_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+namespace {
+
+// Host-side planning: validation, LTS labels, permutation, pass plans.
+lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1, int n2,
+                     double gravity) {
+    lts_status s = validate(c, m);
+    if (s) return s;
+    std::vector<int> cls, ecls;
+    if ((s = label_regions(c, m, fine, n1, n2, cls, ecls))) return s;
+    const int nC = m->n_cells, nE = m->n_edges, nV = m->n_vertices;
+    c->nC = nC;
+    c->nE = nE;
+    c->nV = nV;
+    c->maxE = m->max_edges;
+    c->g = gravity;
+    // cell order: class, then Morton key of the position (or input index)
+    std::vector<uint64_t> key(nC, 0);
+    if (m->cell_xyz) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = 0; i < nC; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], m->cell_xyz[3 * i + d]);
+                hi[d] = std::max(hi[d], m->cell_xyz[3 * i + d]);
+            }
+        for (int i = 0; i < nC; ++i) {
+            uint64_t k = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double span = hi[d] - lo[d];
+                const double f = span > 0 ? (m->cell_xyz[3 * i + d] - lo[d]) / span : 0.0;
+                k |= spread3((uint64_t)std::min(2097151.0, f * 2097151.0)) << d;
+            }
+            key[i] = k;
+        }
+    }
+    c->cperm.resize(nC);
+    std::iota(c->cperm.begin(), c->cperm.end(), 0);
+    std::stable_sort(c->cperm.begin(), c->cperm.end(), [&](int a, int b) {
+        if (cls[a] != cls[b]) return cls[a] < cls[b];
+        return key[a] < key[b];
+    });
+    c->cinv.assign(nC, 0);
+    for (int ni = 0; ni < nC; ++ni) c->cinv[c->cperm[ni]] = ni;
+    for (int k = 0; k < 8; ++k) c->cb[k] = nC;
+    for (int ni = nC - 1; ni >= 0; --ni) c->cb[cls[c->cperm[ni]]] = ni;
+    for (int k = 6; k >= 0; --k) c->cb[k] = std::min(c->cb[k], c->cb[k + 1]);
+    c->cb[7] = nC;
+    // edges: class, then (min cell position, max cell position)
+    c->eperm.resize(nE);
+    std::iota(c->eperm.begin(), c->eperm.end(), 0);
+    auto emin = [&](int e) { return std::min(c->cinv[m->cells_on_edge[2 * e]], c->cinv[m->cells_on_edge[2 * e + 1]]); };
+    auto emax = [&](int e) { return std::max(c->cinv[m->cells_on_edge[2 * e]], c->cinv[m->cells_on_edge[2 * e + 1]]); };
+    std::stable_sort(c->eperm.begin(), c->eperm.end(), [&](int a, int b) {
+        if (ecls[a] != ecls[b]) return ecls[a] < ecls[b];
+        if (emin(a) != emin(b)) return emin(a) < emin(b);
+        return emax(a) < emax(b);
+    });
+    c->einv.assign(nE, 0);
+    for (int ne = 0; ne < nE; ++ne) c->einv[c->eperm[ne]] = ne;
+    for (int k = 0; k < 6; ++k) c->eb[k] = nE;
+    for (int ne = nE - 1; ne >= 0; --ne) c->eb[ecls[c->eperm[ne]]] = ne;
+    for (int k = 4; k >= 0; --k) c->eb[k] = std::min(c->eb[k], c->eb[k + 1]);
+    c->eb[5] = nE;
+    // vertices: smallest then largest position of their cells
+    std::vector<int> vmin(nV), vmax(nV);
+    for (int v = 0; v < nV; ++v) {
+        int a = nC, b = -1;
+        for (int k = 0; k < 3; ++k) {
+            const int ci = c->cinv[m->cells_on_vertex[3 * v + k]];
+            a = std::min(a, ci);
+            b = std::max(b, ci);
+        }
+        vmin[v] = a;
+        vmax[v] = b;
+    }
+    c->vperm.resize(nV);
+    std::iota(c->vperm.begin(), c->vperm.end(), 0);
+    std::stable_sort(c->vperm.begin(), c->vperm.end(), [&](int a, int b) {
+        if (vmin[a] != vmin[b]) return vmin[a] < vmin[b];
+        return vmax[a] < vmax[b];
+    });
+    c->vinv.assign(nV, 0);
+    for (int nv = 0; nv < nV; ++nv) c->vinv[c->vperm[nv]] = nv;
+    make_plans(c, m);
+    return LTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_upload_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1, int n2,
+                           double gravity) {
+    if (!c || !m || !fine) return c ? fail(c, LTS_EINVAL, "NULL argument") : LTS_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, LTS_EDEVICE, "hipSetDevice");
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_device(c);
+    c->has_mesh = c->has_state = c->nonfinite = false;
+    lts_status s = plan_mesh(c, m, fine, n1, n2, gravity);
+    if (s) return s;
+    s = c->prec == LTS_FP64 ? build_device<double>(c, m) : build_device<float>(c, m);
+    if (s) {
+        free_device(c);
+        return s;
+    }
+    c->has_mesh = true;
+    return LTS_OK;
+}
+
+lts_status lts_plan(const lts_mesh* m, const uint8_t* fine, int n1, int n2, int8_t* cell_region,
+                    int8_t* edge_region, uint8_t* cell_fbar, uint8_t* edge_fbar,
+                    int32_t* cell_order, int32_t* edge_order, int32_t* vertex_order,
+                    int32_t* ranges, char* errbuf, int errlen) {
+    if (!m || !fine) return LTS_EINVAL;
+    lts_ctx tmp;
+    lts_status s = plan_mesh(&tmp, m, fine, n1, n2, 9.81);
+    if (s) {
+        if (errbuf && errlen > 0) {
+            std::strncpy(errbuf, tmp.err.c_str(), errlen - 1);
+            errbuf[errlen - 1] = 0;
+        }
+        return s;
+    }
+    if (cell_region) std::copy(tmp.creg.begin(), tmp.creg.end(), cell_region);
+    if (edge_region) std::copy(tmp.ereg.begin(), tmp.ereg.end(), edge_region);
+    if (cell_fbar) std::copy(tmp.cfbar.begin(), tmp.cfbar.end(), cell_fbar);
+    if (edge_fbar) std::copy(tmp.efbar.begin(), tmp.efbar.end(), edge_fbar);
+    if (cell_order) std::copy(tmp.cperm.begin(), tmp.cperm.end(), cell_order);
+    if (edge_order) std::copy(tmp.eperm.begin(), tmp.eperm.end(), edge_order);
+    if (vertex_order) std::copy(tmp.vperm.begin(), tmp.vperm.end(), vertex_order);
+    if (ranges) {
+        int k = 0;
+        for (int j = 0; j < 8; ++j) ranges[k++] = tmp.cb[j];
+        for (int j = 0; j < 6; ++j) ranges[k++] = tmp.eb[j];
+        for (int p = 0; p < P_N; ++p) {
+            const PassPlan& P = tmp.plan[p];
+            const int v[8] = {P.c_lo, P.c_hi, P.v_lo, P.v_hi, P.ct_lo, P.ct_hi, P.et_lo, P.et_hi};
+            for (int j = 0; j < 8; ++j) ranges[k++] = v[j];
+        }
+    }
+    return LTS_OK;
+}
+
+lts_status lts_get_regions(lts_ctx* c, int8_t* cr, int8_t* er, uint8_t* cf, uint8_t* ef) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (cr) std::copy(c->creg.begin(), c->creg.end(), cr);
+    if (er) std::copy(c->ereg.begin(), c->ereg.end(), er);
+    if (cf) std::copy(c->cfbar.begin(), c->cfbar.end(), cf);
+    if (ef) std::copy(c->efbar.begin(), c->efbar.end(), ef);
+    return LTS_OK;
+}
+
+lts_status lts_region_counts(lts_ctx* c, int64_t* cells, int64_t* edges, int64_t* fbar) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (cells) {
+        cells[LTS_F] = c->cb[3];
+        cells[LTS_I1] = c->cb[4] - c->cb[3];
+        cells[LTS_I2] = c->cb[5] - c->cb[4];
+        cells[LTS_C] = c->nC - c->cb[5];
+    }
+    if (edges) {
+        edges[LTS_F] = c->eb[2];
+        edges[LTS_I1] = c->eb[3] - c->eb[2];
+        edges[LTS_I2] = c->eb[4] - c->eb[3];
+        edges[LTS_C] = c->nE - c->eb[4];
+    }
+    if (fbar) {
+        fbar[0] = c->cb[3] - c->cb[1];
+        fbar[1] = c->eb[2] - c->eb[1];
+    }
+    return LTS_OK;
+}
+
+lts_status lts_init_state(lts_ctx* c, const double* h, const double* u, double t0) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (!h || !u) return fail(c, LTS_EINVAL, "NULL state");
+    s = c->prec == LTS_FP64 ? set_state<double>(c, h, u) : set_state<float>(c, h, u);
+    if (s) return s;
+    HIPCHK(c, launch_fill_int(c->flag, 0, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_state = true;
+    c->nonfinite = false;
+    c->t = t0;
+    c->steps = 0;
+    return LTS_OK;
+}
+
+lts_status lts_init_state_device(lts_ctx* c, const void* dh, const void* du, double t0) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (!dh || !du) return fail(c, LTS_EINVAL, "NULL state");
+    const size_t ts = tsize(c);
+    std::vector<char> hh((size_t)c->nC * ts), uu((size_t)c->nE * ts), ph(hh.size()), pu(uu.size());
+    HIPCHK(c, hipMemcpy(hh.data(), dh, hh.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(uu.data(), du, uu.size(), hipMemcpyDeviceToHost));
+    for (int ni = 0; ni < c->nC; ++ni) std::memcpy(&ph[ni * ts], &hh[(size_t)c->cperm[ni] * ts], ts);
+    for (int ne = 0; ne < c->nE; ++ne) std::memcpy(&pu[ne * ts], &uu[(size_t)c->eperm[ne] * ts], ts);
+    HIPCHK(c, hipMemcpy(c->Ah, ph.data(), ph.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->Au, pu.data(), pu.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, launch_fill_int(c->flag, 0, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_state = true;
+    c->nonfinite = false;
+    c->t = t0;
+    c->steps = 0;
+    return LTS_OK;
+}
+
+lts_status lts_step(lts_ctx* c, double dt, int M, int n) {
+    lts_status s = ready(c, true);
+    if (s) return s;
+    if (!(dt > 0) || M < 1 || n < 0) return fail(c, LTS_EINVAL, "need dt > 0, M >= 1, n >= 0");
+    if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
+    if (n == 0) return LTS_OK;
+    s = c->prec == LTS_FP64 ? run_lts<double>(c, dt, M, n) : run_lts<float>(c, dt, M, n);
+    if (s) return s;
+    c->t += dt * n;
+    c->steps += n;
+    return LTS_OK;
+}
+
+lts_status lts_step_rk3(lts_ctx* c, double dt, int n) {
+    lts_status s = ready(c, true);
+    if (s) return s;
+    if (!(dt > 0) || n < 0) return fail(c, LTS_EINVAL, "need dt > 0, n >= 0");
+    if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
+    if (n == 0) return LTS_OK;
+    s = c->prec == LTS_FP64 ? run_rk3<double>(c, dt, n) : run_rk3<float>(c, dt, n);
+    if (s) return s;
+    c->t += dt * n;
+    c->steps += n;
+    return LTS_OK;
+}
+
+lts_status lts_eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, double* du) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (!h || !u || !dh || !du) return fail(c, LTS_EINVAL, "NULL argument");
+    return c->prec == LTS_FP64 ? eval_rhs<double>(c, h, u, dh, du)
+                               : eval_rhs<float>(c, h, u, dh, du);
+}
+
+lts_status lts_diagnostics(lts_ctx* c, lts_diag* out) {
+    lts_status s = ready(c, true);
+    if (s) return s;
+    if (!out) return fail(c, LTS_EINVAL, "NULL output");
+    double d[8] = {0};
+    s = c->prec == LTS_FP64 ? diagnostics<double>(c, d) : diagnostics<float>(c, d);
+    if (s) return s;
+    out->t = c->t;
+    out->mass = d[0];
+    out->energy = d[1];
+    out->h_min = d[2];
+    out->h_max = d[3];
+    out->u_absmax = d[4];
+    out->n_nonfinite = (int64_t)d[5];
+    out->steps = c->steps;
+    if (d[6] != 0 || d[5] != 0) c->nonfinite = true;
+    if (c->nonfinite) return fail(c, LTS_ENONFINITE, "a step produced non-finite values");
+    return LTS_OK;
+}
+
+lts_status lts_get_state(lts_ctx* c, double* h, double* u) {
+    lts_status s = ready(c, true);
+    if (s) return s;
+    return c->prec == LTS_FP64 ? get_state<double>(c, h, u) : get_state<float>(c, h, u);
+}
+
+lts_status lts_get_state_device(lts_ctx* c, void* dh, void* du) {
+    lts_status s = ready(c, true);
+    if (s) return s;
+    if (!dh || !du) return fail(c, LTS_EINVAL, "NULL output");
+    const size_t ts = tsize(c);
+    std::vector<char> hh((size_t)c->nC * ts), uu((size_t)c->nE * ts), ph(hh.size()), pu(uu.size());
+    HIPCHK(c, hipMemcpyAsync(ph.data(), c->Ah, ph.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(pu.data(), c->Au, pu.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int ni = 0; ni < c->nC; ++ni) std::memcpy(&hh[(size_t)c->cperm[ni] * ts], &ph[ni * ts], ts);
+    for (int ne = 0; ne < c->nE; ++ne) std::memcpy(&uu[(size_t)c->eperm[ne] * ts], &pu[ne * ts], ts);
+    HIPCHK(c, hipMemcpy(dh, hh.data(), hh.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(du, uu.data(), uu.size(), hipMemcpyHostToDevice));
+    return LTS_OK;
+}
+
+lts_status lts_set_timing(lts_ctx* c, int enable) {
+    if (!c) return LTS_EINVAL;
+    c->timing = enable != 0;
+    for (int k = 0; k < KC_N; ++k) {
+        c->st_launch[k] = 0;
+        c->st_ms[k] = 0;
+        c->st_bytes[k] = 0;
+    }
+    return LTS_OK;
+}
+
+int lts_kernel_stats(lts_ctx* c, int max_classes, int64_t* launches, double* ms, double* bytes) {
+    if (!c) return 0;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+            c->st_launch[p.cls] += 1;
+            c->st_ms[p.cls] += t;
+            c->st_bytes[p.cls] += p.bytes;
+        }
+        c->evpool.push_back(p.a);
+        c->evpool.push_back(p.b);
+    }
+    c->pending.clear();
+    const int n = std::min(max_classes, (int)KC_N);
+    for (int k = 0; k < n; ++k) {
+        if (launches) launches[k] = c->st_launch[k];
+        if (ms) ms[k] = c->st_ms[k];
+        if (bytes) bytes[k] = c->st_bytes[k];
+    }
+    return n;
+}
+
+}  // extern "C"

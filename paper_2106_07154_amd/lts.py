@@ -1,0 +1,282 @@
+"""ctypes binding of liblts (include/lts.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts numpy
+arrays and torch device tensors to pointers and status codes to exceptions.
+Loading fails loudly when liblts.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblts.so")
+
+LTS_OK, LTS_EINVAL, LTS_EMESH, LTS_ELABEL, LTS_ENONFINITE, LTS_EDEVICE, LTS_ESTATE, LTS_ENOMEM = \
+    0, -1, -2, -3, -4, -5, -6, -7
+LTS_FP64, LTS_FP32 = 0, 1
+LTS_C, LTS_I2, LTS_I1, LTS_F = 0, 1, 2, 3
+KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency", "interface_predict",
+                  "interface_correct", "copy", "diagnostics"]
+
+EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
+            "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_eval_rhs",
+            "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
+            "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy"]
+
+
+class LTSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblts status {status}: {msg}")
+        self.status = status
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("n_vertices", ctypes.c_int32), ("max_edges", ctypes.c_int32)] + [
+        (name, ctypes.c_void_p) for name in (
+            "n_edges_on_cell", "edges_on_cell", "cells_on_cell", "vertices_on_cell",
+            "cells_on_edge", "vertices_on_edge", "edges_on_vertex", "cells_on_vertex",
+            "kite_areas_on_vertex", "area_cell", "area_triangle", "dc_edge", "dv_edge",
+            "f_vertex", "bottom", "cell_xyz")]
+
+
+class _Diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("mass", ctypes.c_double),
+                ("energy", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("h_max", ctypes.c_double), ("u_absmax", ctypes.c_double),
+                ("n_nonfinite", ctypes.c_int64), ("steps", ctypes.c_int64)]
+
+
+@dataclass
+class Diag:
+    t: float
+    mass: float
+    energy: float
+    h_min: float
+    h_max: float
+    u_absmax: float
+    n_nonfinite: int
+    steps: int
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblts.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblts.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    ci, cd = ctypes.c_int, ctypes.c_double
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lts_create": ([PP, ci, ci, P], ci),
+        "lts_upload_mesh": ([P, ctypes.POINTER(_Mesh), P, ci, ci, cd], ci),
+        "lts_get_regions": ([P, P, P, P, P], ci),
+        "lts_init_state": ([P, P, P, cd], ci),
+        "lts_init_state_device": ([P, P, P, cd], ci),
+        "lts_step": ([P, cd, ci, ci], ci),
+        "lts_step_rk3": ([P, cd, ci], ci),
+        "lts_eval_rhs": ([P, P, P, P, P], ci),
+        "lts_diagnostics": ([P, ctypes.POINTER(_Diag)], ci),
+        "lts_get_state": ([P, P, P], ci),
+        "lts_get_state_device": ([P, P, P], ci),
+        "lts_set_timing": ([P, ci], ci),
+        "lts_kernel_stats": ([P, ci, i64p, dp, dp], ci),
+        "lts_region_counts": ([P, i64p, i64p, i64p], ci),
+        "lts_last_error": ([P], ctypes.c_char_p),
+        "lts_destroy": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class LTSContext:
+    """One liblts context: a mesh, its LTS regions and a state on one GPU."""
+
+    def __init__(self, device: int = 0, precision: str = "fp64", stream=None):
+        self._lib = load_library()
+        self.precision = precision
+        prec = {"fp64": LTS_FP64, "fp32": LTS_FP32}[precision]
+        h = ctypes.c_void_p()
+        st = self._lib.lts_create(ctypes.byref(h), int(device), prec,
+                                  ctypes.c_void_p(stream) if stream else None)
+        if st != LTS_OK:
+            raise LTSError(st, "lts_create failed")
+        self._h = h
+        self._keep = []
+        self.mesh = None
+
+    def _check(self, st: int):
+        if st != LTS_OK:
+            msg = self._lib.lts_last_error(self._h)
+            raise LTSError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lts_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---------------------------------------------------------------- mesh
+    def upload_mesh(self, mesh, fine_mask, n_if1: int = 2, n_if2: int = 2,
+                    gravity: float = 9.81, use_positions: bool = True):
+        m, keep = _mesh_struct(mesh, use_positions)
+        fm = np.ascontiguousarray(fine_mask, np.uint8)
+        self._check(self._lib.lts_upload_mesh(self._h, ctypes.byref(m), _ptr(fm), int(n_if1),
+                                              int(n_if2), float(gravity)))
+        self.mesh = mesh
+
+    def regions(self):
+        m = self.mesh
+        cr = np.empty(m.nCells, np.int8)
+        er = np.empty(m.nEdges, np.int8)
+        cf = np.empty(m.nCells, np.uint8)
+        ef = np.empty(m.nEdges, np.uint8)
+        self._check(self._lib.lts_get_regions(self._h, _ptr(cr), _ptr(er), _ptr(cf), _ptr(ef)))
+        return cr, er, cf, ef
+
+    def region_counts(self):
+        c = np.zeros(4, np.int64)
+        e = np.zeros(4, np.int64)
+        f = np.zeros(2, np.int64)
+        P = ctypes.POINTER(ctypes.c_int64)
+        self._check(self._lib.lts_region_counts(self._h, c.ctypes.data_as(P),
+                                                e.ctypes.data_as(P), f.ctypes.data_as(P)))
+        return c, e, f
+
+    # ---------------------------------------------------------------- state
+    def init_state(self, h, u, t0: float = 0.0):
+        h = np.ascontiguousarray(h, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        self._check(self._lib.lts_init_state(self._h, _ptr(h), _ptr(u), float(t0)))
+
+    def init_state_device(self, h_tensor, u_tensor, t0: float = 0.0):
+        self._check(self._lib.lts_init_state_device(self._h, h_tensor.data_ptr(),
+                                                    u_tensor.data_ptr(), float(t0)))
+
+    def get_state(self):
+        h = np.empty(self.mesh.nCells)
+        u = np.empty(self.mesh.nEdges)
+        self._check(self._lib.lts_get_state(self._h, _ptr(h), _ptr(u)))
+        return h, u
+
+    def get_state_device(self, h_tensor, u_tensor):
+        self._check(self._lib.lts_get_state_device(self._h, h_tensor.data_ptr(),
+                                                   u_tensor.data_ptr()))
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, dt_coarse: float, M: int, n_steps: int = 1):
+        self._check(self._lib.lts_step(self._h, float(dt_coarse), int(M), int(n_steps)))
+
+    def step_rk3(self, dt: float, n_steps: int = 1):
+        self._check(self._lib.lts_step_rk3(self._h, float(dt), int(n_steps)))
+
+    def eval_rhs(self, h, u):
+        h = np.ascontiguousarray(h, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        dh = np.empty_like(h)
+        du = np.empty_like(u)
+        self._check(self._lib.lts_eval_rhs(self._h, _ptr(h), _ptr(u), _ptr(dh), _ptr(du)))
+        return dh, du
+
+    def diagnostics(self) -> Diag:
+        d = _Diag()
+        self._check(self._lib.lts_diagnostics(self._h, ctypes.byref(d)))
+        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps)
+
+    def diagnostics_status(self):
+        d = _Diag()
+        st = self._lib.lts_diagnostics(self._h, ctypes.byref(d))
+        return st, Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite,
+                        d.steps)
+
+    # ---------------------------------------------------------------- timing
+    def set_timing(self, enable: bool):
+        self._check(self._lib.lts_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        n = len(KERNEL_CLASSES)
+        la = np.zeros(n, np.int64)
+        ms = np.zeros(n)
+        by = np.zeros(n)
+        k = self._lib.lts_kernel_stats(self._h, n, la.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       by.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return {KERNEL_CLASSES[i]: dict(launches=int(la[i]), ms=float(ms[i]), bytes=float(by[i]))
+                for i in range(k)}
+
+
+def _mesh_struct(mesh, use_positions=True):
+    i32 = lambda a: np.ascontiguousarray(a, np.int32)
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    arrs = dict(
+        n_edges_on_cell=i32(mesh.nEdgesOnCell), edges_on_cell=i32(mesh.edgesOnCell),
+        cells_on_cell=i32(mesh.cellsOnCell), vertices_on_cell=i32(mesh.verticesOnCell),
+        cells_on_edge=i32(mesh.cellsOnEdge), vertices_on_edge=i32(mesh.verticesOnEdge),
+        edges_on_vertex=i32(mesh.edgesOnVertex), cells_on_vertex=i32(mesh.cellsOnVertex),
+        kite_areas_on_vertex=f64(mesh.kiteAreasOnVertex), area_cell=f64(mesh.areaCell),
+        area_triangle=f64(mesh.areaTriangle), dc_edge=f64(mesh.dcEdge),
+        dv_edge=f64(mesh.dvEdge), f_vertex=f64(mesh.fVertex), bottom=f64(mesh.bottom))
+    if use_positions:
+        z = mesh.zCell if getattr(mesh, "zCell", None) is not None else np.zeros(mesh.nCells)
+        arrs["cell_xyz"] = f64(np.stack([mesh.xCell, mesh.yCell, z], 1))
+    m = _Mesh(mesh.nCells, mesh.nEdges, mesh.nVertices, mesh.maxEdges)
+    for k, v in arrs.items():
+        setattr(m, k, _ptr(v))
+    return m, arrs
+
+
+PASS_NAMES = ["full", "step1", "step2", "step3", "step4"]
+
+
+def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = True):
+    """Host-only lts_plan: labels, device ordering and pass ranges (no GPU)."""
+    lib = load_library()
+    if not hasattr(lib, "_plan_typed"):
+        P = ctypes.c_void_p
+        lib.lts_plan.argtypes = [ctypes.POINTER(_Mesh), P, ctypes.c_int, ctypes.c_int] + [P] * 8 + \
+            [ctypes.c_char_p, ctypes.c_int]
+        lib.lts_plan.restype = ctypes.c_int
+        lib._plan_typed = True
+    m, keep = _mesh_struct(mesh, use_positions)
+    fm = np.ascontiguousarray(fine_mask, np.uint8)
+    out = dict(cell_region=np.empty(mesh.nCells, np.int8), edge_region=np.empty(mesh.nEdges, np.int8),
+               cell_fbar=np.empty(mesh.nCells, np.uint8), edge_fbar=np.empty(mesh.nEdges, np.uint8),
+               cell_order=np.empty(mesh.nCells, np.int32), edge_order=np.empty(mesh.nEdges, np.int32),
+               vertex_order=np.empty(mesh.nVertices, np.int32), ranges=np.empty(54, np.int32))
+    err = ctypes.create_string_buffer(512)
+    st = lib.lts_plan(ctypes.byref(m), _ptr(fm), int(n_if1), int(n_if2),
+                      *[_ptr(out[k]) for k in ("cell_region", "edge_region", "cell_fbar",
+                                              "edge_fbar", "cell_order", "edge_order",
+                                              "vertex_order", "ranges")],
+                      err, len(err))
+    if st != LTS_OK:
+        raise LTSError(st, err.value.decode())
+    r = out.pop("ranges")
+    out["cell_class_start"] = r[:8].copy()
+    out["edge_class_start"] = r[8:14].copy()
+    out["passes"] = {name: dict(zip(["c_lo", "c_hi", "v_lo", "v_hi", "ct_lo", "ct_hi",
+                                     "et_lo", "et_hi"], r[14 + 8 * k: 22 + 8 * k].tolist()))
+                     for k, name in enumerate(PASS_NAMES)}
+    return out

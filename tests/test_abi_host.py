@@ -1,0 +1,153 @@
+"""Host-side checks of liblts that need no GPU: the shared library loads and
+exports every entry point of include/lts.h, its mesh validation rejects broken
+meshes, its LTS labels equal the oracle's (bit-exact), and the device ordering
+puts every evaluation set of Algorithm 2.2 in a contiguous range whose reads
+stay inside the cells and edges that hold valid stage values."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as om
+from oracle import Oracle
+from paper_2106_07154_amd import lts
+from paper_2106_07154_amd.inputs import strip_fine_mask
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2106_07154_amd.build import stale, build_lib
+    if stale():
+        build_lib()
+    return lts.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    text = open(os.path.join(ROOT, "include", "lts.h")).read()
+    decl = re.compile(r"^(?:lts_status|void|int|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
+                      re.M)
+    declared = sorted(set(decl.findall(text)))
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(declared) == sorted(lts.EXPORTED)
+
+
+def _cases(request):
+    out = []
+    m = request.getfixturevalue("hex64")
+    out.append((m, strip_fine_mask(m, 28, 35, 1e4), 2, 2))
+    m = request.getfixturevalue("irregular")
+    out.append((m, (np.hypot(m.xCell - m.Lx / 2, m.yCell - m.Ly / 2) < 3.5e4).astype(np.uint8), 2, 1))
+    m = request.getfixturevalue("lloyd_mesh")
+    out.append((m, (np.hypot(m.xCell - 2e5, m.yCell - 2e5) < 5e4).astype(np.uint8), 2, 2))
+    out.append((m, (np.hypot(m.xCell - 2e5, m.yCell - 2e5) < 5e4).astype(np.uint8), 1, 3))
+    return out
+
+
+def test_labels_match_oracle(lib, request):
+    for m, fm, n1, n2 in _cases(request):
+        P = lts.plan(m, fm, n1, n2)
+        R = Oracle(m).regions(fm, n1, n2)
+        assert np.array_equal(P["cell_region"], R.cell)
+        assert np.array_equal(P["edge_region"], R.edge)
+        assert np.array_equal(P["cell_fbar"], R.cell_fbar)
+        assert np.array_equal(P["edge_fbar"], R.edge_fbar)
+
+
+def _reads(m, cells, verts):
+    """Cells and edges read by the cell kernel over `cells` and the vertex
+    kernel over `verts` (caller numbering)."""
+    rc, re_ = set(), set()
+    for i in cells:
+        n = m.nEdgesOnCell[i]
+        rc.add(i)
+        rc.update(m.cellsOnCell[i, :n].tolist())
+        re_.update(m.edgesOnCell[i, :n].tolist())
+    for v in verts:
+        rc.update(m.cellsOnVertex[v].tolist())
+        re_.update(m.edgesOnVertex[v].tolist())
+    return rc, re_
+
+
+def test_ordering_ranges_and_valid_reads(lib, request):
+    for m, fm, n1, n2 in _cases(request):
+        P = lts.plan(m, fm, n1, n2)
+        co, eo, vo = P["cell_order"], P["edge_order"], P["vertex_order"]
+        assert sorted(co) == list(range(m.nCells))
+        assert sorted(eo) == list(range(m.nEdges))
+        assert sorted(vo) == list(range(m.nVertices))
+        cb, eb = P["cell_class_start"], P["edge_class_start"]
+        cpos = np.empty(m.nCells, np.int64)
+        cpos[co] = np.arange(m.nCells)
+        epos = np.empty(m.nEdges, np.int64)
+        epos[eo] = np.arange(m.nEdges)
+        creg, ereg = P["cell_region"][co], P["edge_region"][eo]
+        # classes are contiguous and in region order
+        assert (creg[:cb[3]] == om.F).all() and (creg[cb[3]:cb[4]] == om.I1).all()
+        assert (creg[cb[4]:cb[5]] == om.I2).all() and (creg[cb[5]:] == om.C).all()
+        assert (P["cell_fbar"][co][cb[1]:cb[3]] == 1).all() and (P["cell_fbar"][co][:cb[1]] == 0).all()
+        assert (ereg[:eb[2]] == om.F).all() and (ereg[eb[2]:eb[3]] == om.I1).all()
+        assert (ereg[eb[3]:eb[4]] == om.I2).all() and (ereg[eb[4]:] == om.C).all()
+        assert (P["edge_fbar"][eo][eb[1]:eb[2]] == 1).all() and (P["edge_fbar"][eo][:eb[1]] == 0).all()
+        # F2 then F1 (F1 touches I1), C1 touches I2
+        nb_reg = lambda i: {P["cell_region"][j] for j in m.cellsOnCell[i, :m.nEdgesOnCell[i]]}
+        for k in range(cb[2], cb[3]):
+            assert om.I1 in nb_reg(co[k])
+        for k in range(cb[5], cb[6]):
+            assert om.I2 in nb_reg(co[k])
+        # valid stage values per pass (positions): what each pass may read
+        valid = {
+            "full": (0, 0), "step1": (0, 0),       # reads X0: valid everywhere
+            "step2": (cb[1], eb[1]),               # reads X1: underlined F, I, C
+            "step3": (0, 0),                       # F substep, I1 predicted, X_s elsewhere
+            "step4": (cb[4], eb[3]),               # reads X2 on I2 and C only
+        }
+        for name, pp in P["passes"].items():
+            tc = co[pp["ct_lo"]:pp["ct_hi"]]
+            te = eo[pp["et_lo"]:pp["et_hi"]]
+            cover = co[pp["c_lo"]:pp["c_hi"]]
+            verts = vo[pp["v_lo"]:pp["v_hi"]]
+            # the cell range covers targets and both cells of every target edge
+            need = set(tc.tolist()) | set(m.cellsOnEdge[te].reshape(-1).tolist())
+            assert need <= set(cover.tolist()), name
+            # the vertex range covers every vertex of the covered cells
+            needv = set()
+            for i in cover:
+                needv.update(m.verticesOnCell[i, :m.nEdgesOnCell[i]].tolist())
+            assert needv <= set(verts.tolist()), name
+            rc, re_ = _reads(m, cover, verts)
+            vc, ve = valid[name]
+            assert cpos[list(rc)].min() >= vc, name
+            assert epos[list(re_)].min() >= ve, name
+
+
+def test_rejects_broken_meshes(lib, hex8):
+    fm = strip_fine_mask(hex8, 2, 3, 1e4)
+    m = hex8.copy()
+    m.cellsOnEdge[5] = m.cellsOnEdge[5][::-1].copy()
+    m.cellsOnEdge[5, 0] = (m.cellsOnEdge[5, 0] + 1) % m.nCells
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm)
+    assert ei.value.status == lts.LTS_EMESH
+    m = hex8.copy()
+    m.edgesOnVertex[3, 1] = m.edgesOnVertex[40, 0]
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm)
+    assert ei.value.status == lts.LTS_EMESH
+    m = hex8.copy()
+    m.kiteAreasOnVertex[0, 0] = -1.0
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm)
+    assert ei.value.status == lts.LTS_EMESH
+    for bad in (np.zeros(hex8.nCells, np.uint8), np.ones(hex8.nCells, np.uint8)):
+        with pytest.raises(lts.LTSError) as ei:
+            lts.plan(hex8, bad)
+        assert ei.value.status == lts.LTS_ELABEL
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(hex8, fm, 0, 2)
+    assert ei.value.status == lts.LTS_ELABEL

@@ -141,12 +141,13 @@ lts_status lts_get_state(lts_ctx *ctx, double *h, double *u);
 /* Copy the state to device arrays in the context precision (caller numbering). */
 lts_status lts_get_state_device(lts_ctx *ctx, void *d_h, void *d_u);
 
-/* Per-kernel timing: when enabled, steps launch without graphs and bracket each
-   kernel with HIP events; lts_kernel_stats reports, per kernel class, the
-   number of launches, total milliseconds and the algorithmic bytes moved (see
-   the library documentation for the byte model).  Classes: 0 vertex PV,
-   1 cell tendency, 2 edge tendency, 3 interface prediction, 4 interface
-   correction, 5 copies.  Returns the number of classes written. */
+/* Per-kernel timing: when enabled, steps launch without graphs and every
+   kernel is launched with start/stop events stamped by the GPU at the kernel's
+   own start and end; lts_kernel_stats reports per kernel class the number of
+   launches, total milliseconds and algorithmic bytes (every array element a
+   launch needs, read or written once).  Classes: 0 vertex potential vorticity,
+   1 cell tendency, 2 edge tendency (with the interface prediction and
+   correction blocks it carries).  Returns the number of classes written. */
 lts_status lts_set_timing(lts_ctx *ctx, int enable);
 int lts_kernel_stats(lts_ctx *ctx, int max_classes, int64_t *launches, double *ms,
                      double *bytes);

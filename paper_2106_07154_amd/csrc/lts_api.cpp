@@ -89,6 +89,12 @@ struct lts_ctx {
     double t = 0.0;
     int64_t steps = 0;
 
+    // perturbation thickness form (FP32): state holds eta = h - href
+    bool pert = false;
+    std::vector<double> href_host;           // device order, value of the stored href
+    std::vector<double> bot_perm, area_perm; // device order
+    void *d_href = nullptr, *d_beta = nullptr;
+
     // graph cache for one coarse step
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -298,9 +304,38 @@ lts_status upload_vec(lts_ctx* c, const T** dst, const std::vector<T>& v) {
     return LTS_OK;
 }
 
+// Perturbation form: href_i = H_s - b_i rounded to T, beta_i = href_i + b_i - H_s
+// (the rounding residue), so the stored eta = h - href is small and
+// g(h + b) = g(eta + beta) + g H_s.
+template <typename T>
+lts_status set_reference(lts_ctx* c, double Hs) {
+    const int nC = c->nC;
+    std::vector<T> hr(nC), be(nC);
+    c->href_host.assign(nC, 0.0);
+    for (int i = 0; i < nC; ++i) {
+        hr[i] = (T)(Hs - c->bot_perm[i]);
+        c->href_host[i] = (double)hr[i];
+        be[i] = (T)((double)hr[i] + c->bot_perm[i] - Hs);
+    }
+    HIPCHK(c, hipMemcpy(c->d_href, hr.data(), nC * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_beta, be.data(), nC * sizeof(T), hipMemcpyHostToDevice));
+    return LTS_OK;
+}
+
+// Reference surface from a state in device order: area-weighted mean of h + b.
+double mean_surface(const lts_ctx* c, const std::vector<double>& h) {
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < c->nC; ++i) {
+        num += c->area_perm[i] * (h[i] + c->bot_perm[i]);
+        den += c->area_perm[i];
+    }
+    return num / den;
+}
+
 template <typename T>
 lts_status build_device(lts_ctx* c, const lts_mesh* m) {
-    const int nC = c->nC, nE = c->nE, nV = c->nV, mx = c->maxE;
+    const int nC = c->nC, nE = c->nE, nV = c->nV;
+    const int mx = padded_slots(c->maxE);  // slot tables padded to the kernel's slot count
     const int* cinv = c->cinv.data();
     const int* einv = c->einv.data();
     const int* vinv = c->vinv.data();
@@ -330,6 +365,13 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
                 if (m->cells_on_vertex[3 * v + k] == i) kite = m->kite_areas_on_vertex[3 * v + k];
             kf[o] = kite / m->area_cell[i];
         }
+        // padding slots: repeat the last real slot's indices, zero coefficients
+        for (int j = n; j < mx; ++j) {
+            const size_t o = (size_t)j * nC + ni, ol = (size_t)(n - 1) * nC + ni;
+            eoc[o] = eoc[ol];
+            coc[o] = coc[ol];
+            voc[o] = voc[ol];
+        }
     }
     std::vector<int32_t> eov((size_t)3 * nV), cov((size_t)3 * nV);
     std::vector<double> tdc((size_t)3 * nV), kite((size_t)3 * nV), fA(nV);
@@ -351,7 +393,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     dm->nC = nC;
     dm->nE = nE;
     dm->nV = nV;
-    dm->maxE = mx;
+    dm->maxE = c->maxE;
     lts_status s;
     if ((s = upload_vec<int32_t>(c, &dm->nEoC, nEoC))) return s;
     if ((s = upload_vec<int32_t>(c, &dm->eoc, eoc))) return s;
@@ -363,6 +405,22 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     if ((s = upload_vec<T>(c, &dm->kf, conv<T>(kf)))) return s;
     if ((s = upload_vec<T>(c, &dm->area, conv<T>(area)))) return s;
     if ((s = upload_vec<T>(c, &dm->bot, conv<T>(bot)))) return s;
+    c->bot_perm = bot;
+    c->area_perm = area;
+    c->pert = sizeof(T) < sizeof(double);
+    if (c->pert) {
+        void* p = nullptr;
+        if ((s = dalloc(c, &p, nC * sizeof(T)))) return s;
+        c->d_href = p;
+        if ((s = dalloc(c, &p, nC * sizeof(T)))) return s;
+        c->d_beta = p;
+        dm->href = static_cast<const T*>(c->d_href);
+        dm->beta = static_cast<const T*>(c->d_beta);
+        if ((s = set_reference<T>(c, 0.0))) return s;
+    } else {
+        dm->href = nullptr;
+        dm->beta = dm->bot;
+    }
     if ((s = upload_vec<int32_t>(c, &dm->eov, eov))) return s;
     if ((s = upload_vec<int32_t>(c, &dm->cov, cov))) return s;
     if ((s = upload_vec<T>(c, &dm->tdc, conv<T>(tdc)))) return s;
@@ -479,32 +537,23 @@ struct Run {
     hipStream_t s;
     bool timed;
 
-    lts_status begin(hipEvent_t* ev) {
+    // Two events for an event-stamped launch (timing mode only).
+    lts_status events(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
         if (!timed) return LTS_OK;
-        if (c->evpool.size() < 2) {
-            for (int k = 0; k < 64; ++k) {
-                hipEvent_t e;
-                HIPCHK(c, hipEventCreate(&e));
-                c->evpool.push_back(e);
-            }
-        }
-        *ev = c->evpool.back();
-        c->evpool.pop_back();
-        HIPCHK(c, hipEventRecord(*ev, s));
-        return LTS_OK;
-    }
-    lts_status end(int cls, hipEvent_t a, double bytes) {
-        if (!timed) return LTS_OK;
-        if (c->evpool.empty()) {
+        while (c->evpool.size() < 2) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->evpool.push_back(e);
         }
-        hipEvent_t b = c->evpool.back();
+        *a = c->evpool.back();
         c->evpool.pop_back();
-        HIPCHK(c, hipEventRecord(b, s));
-        c->pending.push_back({cls, a, b, bytes});
+        *b = c->evpool.back();
+        c->evpool.pop_back();
         return LTS_OK;
+    }
+    void done(int cls, hipEvent_t a, hipEvent_t b, double bytes) {
+        if (timed) c->pending.push_back({cls, a, b, bytes});
     }
 
     static double seg_bytes(const Seg<T>& g) {
@@ -516,32 +565,33 @@ struct Run {
 
     // One right-hand-side pass of kind p over state (h, u) with epilogues.
     lts_status pass(int p, const T* h, const T* u, const Seg<T>& cs0, const Seg<T>& cs1,
-                    const Seg<T>& es0, const Seg<T>& es1) {
+                    const Seg<T>& es0, const Seg<T>& es1, const Aux<T>& aux = Aux<T>()) {
         const PassPlan& P = c->plan[p];
         T* q = static_cast<T*>(c->q);
         T* zs = static_cast<T*>(c->zs);
         const double ts = sizeof(T);
-        hipEvent_t ev = nullptr;
+        hipEvent_t e0, e1;
         lts_status st;
         // vertex PV
-        if ((st = begin(&ev))) return st;
-        HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s));
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
         const double nv = P.v_hi - P.v_lo;
-        if ((st = end(KC_VERTEX, ev, nv * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts)))
-            return st;
+        done(KC_VERTEX, e0, e1, nv * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts);
         // cell tendency + partials
-        if ((st = begin(&ev))) return st;
-        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag, s));
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag, s,
+                                 e0, e1));
         const double ncell = P.c_hi - P.c_lo;
         const double cb = ncell * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
                           (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(cs0) +
                           seg_bytes(cs1);
-        if ((st = end(KC_CELL, ev, cb))) return st;
-        // edge tendency
-        if ((st = begin(&ev))) return st;
-        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, c->flag, s));
-        const double eb = (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(es0) + seg_bytes(es1);
-        if ((st = end(KC_EDGE, ev, eb))) return st;
+        done(KC_CELL, e0, e1, cb);
+        // edge tendency (+ appended element-wise job)
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1));
+        const double eb = (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(es0) + seg_bytes(es1) +
+                          (aux.kind == 1 ? 4.0 : aux.kind == 2 ? 3.0 : 0.0) * (aux.nh + aux.nu) * ts;
+        done(KC_EDGE, e0, e1, eb);
         return LTS_OK;
     }
 
@@ -559,6 +609,45 @@ struct Run {
         g.a_dt = (T)a_dt;
         return g;
     }
+    static Seg<T> mirror(Seg<T> g, int mlo, int mhi, T* mnew, T* mcur) {
+        g.mlo = mlo;
+        g.mhi = mhi;
+        g.mnew = mnew;
+        g.mcur = mcur;
+        return g;
+    }
+    Aux<T> predict_aux(T* xh, T* xu, int stage, int k, int M) {
+        Aux<T> x;
+        double cf[3];
+        predict_coeffs(stage, k, M, cf);
+        x.kind = 1;
+        x.nh = c->cb[4] - c->cb[3];
+        x.nu = c->eb[3] - c->eb[2];
+        x.lo_h = c->cb[3];
+        x.lo_u = c->eb[2];
+        x.xh = xh;
+        x.xu = xu;
+        x.ah = (T*)c->x0h; x.bh = (T*)c->x1h; x.ch = (T*)c->x2h;
+        x.au = (T*)c->x0u; x.bu = (T*)c->x1u; x.cu = (T*)c->x2u;
+        x.c0 = cf[0]; x.c1 = cf[1]; x.c2 = cf[2];
+        return x;
+    }
+    Aux<T> correct_aux(double delta) {
+        Aux<T> x;
+        x.kind = 2;
+        x.nh = c->cb[5] - c->cb[3];
+        x.nu = c->eb[4] - c->eb[2];
+        x.nbh = c->cb[4] - c->cb[3];
+        x.nbu = c->eb[3] - c->eb[2];
+        x.lo_h = c->cb[3];
+        x.lo_u = c->eb[2];
+        x.xh = (T*)c->Ah;
+        x.xu = (T*)c->Au;
+        x.ah = (T*)c->x0h; x.bh = (T*)c->acch;
+        x.au = (T*)c->x0u; x.bu = (T*)c->accu;
+        x.c0 = delta;
+        return x;
+    }
     static Seg<T> accum(int lo, int hi, T* acc, double theta, bool first) {
         Seg<T> g;
         g.lo = lo;
@@ -570,26 +659,10 @@ struct Run {
         return g;
     }
 
-    lts_status predict(T* xh, T* xu, const double cf[3]) {
-        hipEvent_t ev = nullptr;
-        lts_status st;
-        if ((st = begin(&ev))) return st;
-        const int nh = c->cb[4] - c->cb[3], nu = c->eb[3] - c->eb[2];
-        HIPCHK(c, launch_predict<T>(xh, (T*)c->x0h, (T*)c->x1h, (T*)c->x2h, c->cb[3], nh, xu,
-                                    (T*)c->x0u, (T*)c->x1u, (T*)c->x2u, c->eb[2], nu, cf[0],
-                                    cf[1], cf[2], s));
-        return end(KC_PREDICT, ev, (nh + nu) * 4.0 * sizeof(T));
-    }
-    lts_status copy_i1(T* dh, const T* sh, T* du, const T* su) {
-        hipEvent_t ev = nullptr;
-        lts_status st;
-        if ((st = begin(&ev))) return st;
-        const int nh = c->cb[4] - c->cb[3], nu = c->eb[3] - c->eb[2];
-        HIPCHK(c, launch_copy<T>(dh, sh, c->cb[3], nh, du, su, c->eb[2], nu, s));
-        return end(KC_COPY, ev, (nh + nu) * 2.0 * sizeof(T));
-    }
-
-    // Algorithm 2.2, order 3: one coarse step on the state in A.
+    // Algorithm 2.2, order 3: one coarse step on the state in A.  The
+    // interface-1 copies of X0, X1, X2 are written by the stage epilogues; each
+    // interface-1 prediction and the final interface correction run as extra
+    // blocks of the preceding edge kernel (they touch none of its data).
     lts_status lts3_step(double dt, int M) {
         T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
           *Cu = (T*)c->Cu;
@@ -600,60 +673,56 @@ struct Run {
         const Seg<T> none;
         lts_status st;
         // Step 1: first stage with dt on underlined F, I1, I2, C
-        if ((st = pass(P_STEP1, Ah, Au, upd(cb[1], nC, Bh, nullptr, 0, Ah, 1, dt), none,
-                       upd(eb[1], nE, Bu, nullptr, 0, Au, 1, dt), none)))
+        if ((st = pass(P_STEP1, Ah, Au,
+                       mirror(upd(cb[1], nC, Bh, nullptr, 0, Ah, 1, dt), cb[3], cb[4],
+                              (T*)c->x1h, (T*)c->x0h),
+                       none,
+                       mirror(upd(eb[1], nE, Bu, nullptr, 0, Au, 1, dt), eb[2], eb[3],
+                              (T*)c->x1u, (T*)c->x0u),
+                       none)))
             return st;
-        if ((st = copy_i1((T*)c->x0h, Ah, (T*)c->x0u, Au))) return st;
-        if ((st = copy_i1((T*)c->x1h, Bh, (T*)c->x1u, Bu))) return st;
         // Step 2: second stage with dt on I1, I2, C
-        if ((st = pass(P_STEP2, Bh, Bu, upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), none,
-                       upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), none)))
+        if ((st = pass(P_STEP2, Bh, Bu,
+                       mirror(upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), cb[3], cb[4],
+                              (T*)c->x2h, nullptr),
+                       none,
+                       mirror(upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), eb[2], eb[3],
+                              (T*)c->x2u, nullptr),
+                       none)))
             return st;
-        if ((st = copy_i1((T*)c->x2h, Ch, (T*)c->x2u, Cu))) return st;
-        // Step 3: M fine SSPRK3 substeps on F; I1 predicted, I accumulates
-        double cf[3];
+        // Step 3: M fine SSPRK3 substeps on F; I1 predicted, I accumulates.
+        // (Stage (old,0) needs no prediction: its coefficients give X0.)
         for (int k = 0; k < M; ++k) {
             // stage (old,k): A holds F at substep k, X0 on I2 and C
-            if (k > 0) {
-                predict_coeffs(0, k, M, cf);
-                if ((st = predict(Ah, Au, cf))) return st;
-            }
             if ((st = pass(P_STEP3, Ah, Au, upd(0, cb[3], Bh, nullptr, 0, Ah, 1, delta),
                            accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, k == 0),
                            upd(0, eb[2], Bu, nullptr, 0, Au, 1, delta),
-                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, k == 0))))
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, k == 0),
+                           predict_aux(Bh, Bu, 1, k, M))))
                 return st;
             // stage (1st,k): B holds stage-1 F, X1 on I2 and C
-            predict_coeffs(1, k, M, cf);
-            if ((st = predict(Bh, Bu, cf))) return st;
             if ((st = pass(P_STEP3, Bh, Bu, upd(0, cb[3], Ch, Ah, 0.75, Bh, 0.25, 0.25 * delta),
                            accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, false),
                            upd(0, eb[2], Cu, Au, 0.75, Bu, 0.25, 0.25 * delta),
-                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, false))))
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, false),
+                           predict_aux(Ch, Cu, 2, k, M))))
                 return st;
             // stage (2nd,k): C holds stage-2 F, X2 on I2 and C; new F into A
-            predict_coeffs(2, k, M, cf);
-            if ((st = predict(Ch, Cu, cf))) return st;
             if ((st = pass(P_STEP3, Ch, Cu,
                            upd(0, cb[3], Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * delta),
                            accum(cb[3], cb[5], (T*)c->acch, 2.0 / 3.0, false),
                            upd(0, eb[2], Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * delta),
-                           accum(eb[2], eb[4], (T*)c->accu, 2.0 / 3.0, false))))
+                           accum(eb[2], eb[4], (T*)c->accu, 2.0 / 3.0, false),
+                           k + 1 < M ? predict_aux(Ah, Au, 0, k + 1, M) : Aux<T>())))
                 return st;
         }
-        // Step 4: third stage with dt on C (reads X2 in C and I2 only)
-        if ((st = pass(P_STEP4, Ch, Cu,
-                       upd(cb[5], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
-                       upd(eb[4], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none)))
-            return st;
-        // Step 5: interface correction x = x_old + dt/M * acc on I1 u I2
-        hipEvent_t ev = nullptr;
-        if ((st = begin(&ev))) return st;
-        const int nIc = cb[5] - cb[3], nIe = eb[4] - eb[2];
-        HIPCHK(c, launch_correct<T>(Ah, (T*)c->x0h, (T*)c->acch, cb[3], nIc, cb[4] - cb[3], Au,
-                                    (T*)c->x0u, (T*)c->accu, eb[2], nIe, eb[3] - eb[2], delta,
-                                    s));
-        return end(KC_CORRECT, ev, (nIc + nIe) * 3.0 * sizeof(T));
+        // Step 4: third stage with dt on C (reads X2 in C and I2 only); Step 5,
+        // the interface correction x = x_old + dt/M * acc on I1 u I2, rides on
+        // its edge kernel.
+        return pass(P_STEP4, Ch, Cu,
+                    upd(cb[5], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
+                    upd(eb[4], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
+                    correct_aux(delta));
     }
 
     // Algorithm 2.1, SSPRK3, over the whole mesh.
@@ -770,7 +839,8 @@ template <typename T>
 lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, double* du) {
     const int nC = c->nC, nE = c->nE;
     std::vector<T> hh(nC), uu(nE);
-    for (int ni = 0; ni < nC; ++ni) hh[ni] = (T)h[c->cperm[ni]];
+    for (int ni = 0; ni < nC; ++ni)
+        hh[ni] = (T)(h[c->cperm[ni]] - (c->pert ? c->href_host[ni] : 0.0));
     for (int ne = 0; ne < nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
     HIPCHK(c, hipMemcpyAsync(c->Bh, hh.data(), nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->Bu, uu.data(), nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
@@ -793,7 +863,14 @@ lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, do
 template <typename T>
 lts_status set_state(lts_ctx* c, const double* h, const double* u) {
     std::vector<T> hh(c->nC), uu(c->nE);
-    for (int ni = 0; ni < c->nC; ++ni) hh[ni] = (T)h[c->cperm[ni]];
+    if (c->pert) {
+        std::vector<double> hp(c->nC);
+        for (int ni = 0; ni < c->nC; ++ni) hp[ni] = h[c->cperm[ni]];
+        lts_status s = set_reference<T>(c, mean_surface(c, hp));
+        if (s) return s;
+    }
+    for (int ni = 0; ni < c->nC; ++ni)
+        hh[ni] = (T)(h[c->cperm[ni]] - (c->pert ? c->href_host[ni] : 0.0));
     for (int ne = 0; ne < c->nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
     HIPCHK(c, hipMemcpyAsync(c->Ah, hh.data(), c->nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->Au, uu.data(), c->nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
@@ -807,7 +884,9 @@ lts_status get_state(lts_ctx* c, double* h, double* u) {
     HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ah, c->nC * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(uu.data(), c->Au, c->nE * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (h) for (int ni = 0; ni < c->nC; ++ni) h[c->cperm[ni]] = (double)hh[ni];
+    if (h)
+        for (int ni = 0; ni < c->nC; ++ni)
+            h[c->cperm[ni]] = (double)hh[ni] + (c->pert ? c->href_host[ni] : 0.0);
     if (u) for (int ne = 0; ne < c->nE; ++ne) u[c->eperm[ne]] = (double)uu[ne];
     return LTS_OK;
 }
@@ -1073,21 +1152,18 @@ lts_status lts_init_state_device(lts_ctx* c, const void* dh, const void* du, dou
     lts_status s = ready(c, false);
     if (s) return s;
     if (!dh || !du) return fail(c, LTS_EINVAL, "NULL state");
-    const size_t ts = tsize(c);
-    std::vector<char> hh((size_t)c->nC * ts), uu((size_t)c->nE * ts), ph(hh.size()), pu(uu.size());
-    HIPCHK(c, hipMemcpy(hh.data(), dh, hh.size(), hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(uu.data(), du, uu.size(), hipMemcpyDeviceToHost));
-    for (int ni = 0; ni < c->nC; ++ni) std::memcpy(&ph[ni * ts], &hh[(size_t)c->cperm[ni] * ts], ts);
-    for (int ne = 0; ne < c->nE; ++ne) std::memcpy(&pu[ne * ts], &uu[(size_t)c->eperm[ne] * ts], ts);
-    HIPCHK(c, hipMemcpy(c->Ah, ph.data(), ph.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->Au, pu.data(), pu.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, launch_fill_int(c->flag, 0, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->has_state = true;
-    c->nonfinite = false;
-    c->t = t0;
-    c->steps = 0;
-    return LTS_OK;
+    std::vector<double> h(c->nC), u(c->nE);
+    if (c->prec == LTS_FP64) {
+        HIPCHK(c, hipMemcpy(h.data(), dh, c->nC * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(u.data(), du, c->nE * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> hf(c->nC), uf(c->nE);
+        HIPCHK(c, hipMemcpy(hf.data(), dh, c->nC * sizeof(float), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(uf.data(), du, c->nE * sizeof(float), hipMemcpyDeviceToHost));
+        std::copy(hf.begin(), hf.end(), h.begin());
+        std::copy(uf.begin(), uf.end(), u.begin());
+    }
+    return lts_init_state(c, h.data(), u.data(), t0);
 }
 
 lts_status lts_step(lts_ctx* c, double dt, int M, int n) {
@@ -1154,15 +1230,16 @@ lts_status lts_get_state_device(lts_ctx* c, void* dh, void* du) {
     lts_status s = ready(c, true);
     if (s) return s;
     if (!dh || !du) return fail(c, LTS_EINVAL, "NULL output");
-    const size_t ts = tsize(c);
-    std::vector<char> hh((size_t)c->nC * ts), uu((size_t)c->nE * ts), ph(hh.size()), pu(uu.size());
-    HIPCHK(c, hipMemcpyAsync(ph.data(), c->Ah, ph.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(pu.data(), c->Au, pu.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int ni = 0; ni < c->nC; ++ni) std::memcpy(&hh[(size_t)c->cperm[ni] * ts], &ph[ni * ts], ts);
-    for (int ne = 0; ne < c->nE; ++ne) std::memcpy(&uu[(size_t)c->eperm[ne] * ts], &pu[ne * ts], ts);
-    HIPCHK(c, hipMemcpy(dh, hh.data(), hh.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(du, uu.data(), uu.size(), hipMemcpyHostToDevice));
+    std::vector<double> h(c->nC), u(c->nE);
+    if ((s = lts_get_state(c, h.data(), u.data()))) return s;
+    if (c->prec == LTS_FP64) {
+        HIPCHK(c, hipMemcpy(dh, h.data(), c->nC * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(du, u.data(), c->nE * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> hf(h.begin(), h.end()), uf(u.begin(), u.end());
+        HIPCHK(c, hipMemcpy(dh, hf.data(), c->nC * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(du, uf.data(), c->nE * sizeof(float), hipMemcpyHostToDevice));
+    }
     return LTS_OK;
 }
 

@@ -24,7 +24,13 @@ struct DevMesh {
     const T* kc;           // [maxE][nC] l_e d_e / (4 A_i)
     const T* kf;           // [maxE][nC] A_{i,v_j} / A_i (kite fraction of vertex slot j)
     const T* area;         // [nC] A_i
-    const T* bot;          // [nC] b_i
+    const T* bot;          // [nC] b_i (diagnostics)
+    // Thickness storage.  href == nullptr: the state holds h itself and
+    // beta = b.  Otherwise the state holds eta = h - href (perturbation form,
+    // used in FP32) and beta = href + b - H_s, so g(h + b) = g(eta + beta) +
+    // const and the constant drops out of every gradient.
+    const T* href;         // [nC] or nullptr
+    const T* beta;         // [nC]
     const int32_t* eov;    // [3][nV]
     const int32_t* cov;    // [3][nV]
     const T* tdc;          // [3][nV] t_{e,v} d_e
@@ -35,6 +41,9 @@ struct DevMesh {
 // One epilogue segment: targets [lo, hi) of a tendency kernel.
 //   mode 1 (update):     out[j] = a_old*xold[j] + a_cur*xcur[j] + a_dt*G
 //   mode 2 (accumulate): acc[j-lo] = (first ? 0 : acc[j-lo]) + theta*G
+//   mirror (update only): for j in [mlo, mhi) also store the new value to
+//   mnew[j-mlo] and the current value xcur[j] to mcur[j-mlo] (either may be
+//   null) -- the interface-1 copies of the coarse stages.
 template <typename T>
 struct Seg {
     int lo = 0, hi = 0, mode = 0, first = 0;
@@ -44,36 +53,48 @@ struct Seg {
     T a_old = 0, a_cur = 0, a_dt = 0;
     T* acc = nullptr;
     T theta = 0;
+    int mlo = 0, mhi = 0;
+    T* mnew = nullptr;
+    T* mcur = nullptr;
 };
 
-enum KernelClass { KC_VERTEX = 0, KC_CELL = 1, KC_EDGE = 2, KC_PREDICT = 3,
-                   KC_CORRECT = 4, KC_COPY = 5, KC_DIAG = 6, KC_N = 7 };
+// Element-wise work appended to an edge-kernel launch as extra blocks:
+//   kind 1 (predict): x[lo+j] = c0 a[j] + c1 b[j] + c2 c[j] in FP64 on the
+//                     interface-1 cells (field h) and edges (field u);
+//   kind 2 (correct): x[lo+j] = (j < nbase ? base[j] : x[lo+j]) + delta acc[j]
+//                     on I1 u I2 cells and edges.
+template <typename T>
+struct Aux {
+    int kind = 0;
+    int nh = 0, nu = 0, lo_h = 0, lo_u = 0, nbh = 0, nbu = 0;
+    T *xh = nullptr, *xu = nullptr;
+    const T *ah = nullptr, *bh = nullptr, *ch = nullptr;
+    const T *au = nullptr, *bu = nullptr, *cu = nullptr;
+    double c0 = 0, c1 = 0, c2 = 0;
+};
+
+enum KernelClass { KC_VERTEX = 0, KC_CELL = 1, KC_EDGE = 2, KC_N = 3 };
 
 // Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch error.
+// Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch
+// error.  With non-null ev0/ev1 the launch goes through hipExtLaunchKernelGGL,
+// which stamps the kernel's own start and end into the two events (timing mode;
+// never used while a graph is being captured).
 template <typename T>
 hipError_t launch_vertex(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo,
-                         int v_hi, hipStream_t s);
+                         int v_hi, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs,
                        int c_lo, int c_hi, T g, const Seg<T>& s0, const Seg<T>& s1,
-                       int* flag, hipStream_t s);
+                       int* flag, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0,
-                       const Seg<T>& s1, int* flag, hipStream_t s);
-// x[lo + j] = c0*a[j] + c1*b[j] + c2*c[j] in FP64, j < n, for two fields.
-template <typename T>
-hipError_t launch_predict(T* xh, const T* ah, const T* bh, const T* ch, int lo_h, int nh,
-                          T* xu, const T* au, const T* bu, const T* cu, int lo_u, int nu,
-                          double c0, double c1, double c2, hipStream_t s);
-// dst[j] = src[lo + j], j < n, for two fields.
-template <typename T>
-hipError_t launch_copy(T* dh, const T* sh, int lo_h, int nh, T* du, const T* su, int lo_u,
-                       int nu, hipStream_t s);
-// x[lo+j] = (j < nbase ? base[j] : x[lo+j]) + delta*acc[j], j < n, two fields.
-template <typename T>
-hipError_t launch_correct(T* xh, const T* baseh, const T* acch, int lo_h, int nh, int nbh,
-                          T* xu, const T* baseu, const T* accu, int lo_u, int nu, int nbu,
-                          double delta, hipStream_t s);
+                       const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Number of cell slots the device tables are padded to for a mesh with maxE.
+int padded_slots(int maxE);
 // Diagnostics partials per block (mass, energy, h_min, h_max, |u|max, nonfinite)
 // then a single-block deterministic reduction into out[8] (doubles).
 template <typename T>

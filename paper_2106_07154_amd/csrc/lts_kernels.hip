@@ -24,6 +24,7 @@
 // Stage arithmetic (Algorithms 2.1 and 2.2) is fused into the cell and edge
 // kernels as epilogue segments: an SSPRK stage update, or accumulation of the
 // interface correction terms already weighted by theta.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lts_internal.h"
@@ -34,6 +35,14 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Blocks are dispatched round-robin over the 8 XCDs; remap so every XCD works
+// on one contiguous chunk of the range and neighbouring blocks share its L2.
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <typename T>
 __device__ __forceinline__ void apply_seg(int j, T G, const Seg<T>& s, int* flag) {
     T v;
@@ -42,6 +51,10 @@ __device__ __forceinline__ void apply_seg(int j, T G, const Seg<T>& s, int* flag
         if (s.xold) v = s.a_old * s.xold[j] + (s.xcur ? s.a_cur * s.xcur[j] : T(0)) + v;
         else if (s.xcur) v = s.a_cur * s.xcur[j] + v;
         s.out[j] = v;
+        if (j >= s.mlo && j < s.mhi) {
+            if (s.mnew) s.mnew[j - s.mlo] = v;
+            if (s.mcur) s.mcur[j - s.mlo] = s.xcur[j];
+        }
     } else {
         const int k = j - s.lo;
         v = s.theta * G;
@@ -62,75 +75,87 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __restrict__ h,
                                                    const T* __restrict__ u, T* __restrict__ q,
                                                    int v_lo, int v_hi) {
-    const int v = v_lo + blockIdx.x * kBlock + threadIdx.x;
+    const int v = v_lo + xcd_block() * kBlock + threadIdx.x;
     if (v >= v_hi) return;
     const int nV = m.nV;
     T circ = 0, hv = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int o = k * nV + v;
+        const int c = m.cov[o];
         circ += m.tdc[o] * u[m.eov[o]];
-        hv += m.kite[o] * h[m.cov[o]];
+        hv += m.kite[o] * (m.href ? m.href[c] + h[c] : h[c]);
     }
     q[v] = (m.fA[v] + circ) / hv;
 }
 
+// Slots n..NE-1 of every cell are padding: valid indices (copies of slot
+// n-1) and zero coefficients, so the kernel runs without per-slot branches and
+// issues every gather of a cell up front.
 template <typename T, int NE>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
                                                  int* flag) {
-    const int i = c_lo + blockIdx.x * kBlock + threadIdx.x;
+    const int i = c_lo + xcd_block() * kBlock + threadIdx.x;
     if (i >= c_hi) return;
     const int nC = m.nC;
+    const int32_t* __restrict__ eoc = m.eoc;
+    const int32_t* __restrict__ coc = m.coc;
+    const int32_t* __restrict__ voc = m.voc;
+    const T* __restrict__ nlp = m.nl;
+    const T* __restrict__ kcp = m.kc;
+    const T* __restrict__ kfp = m.kf;
+    const T* __restrict__ href = m.href;
     const int n = m.nEoC[i];
-    const T hi = h[i];
+    int ed[NE], nb[NE], vx[NE];
+    T nl[NE], kc[NE], kf[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+        const size_t o = (size_t)a * nC + i;
+        ed[a] = eoc[o];
+        nb[a] = coc[o];
+        vx[a] = voc[o];
+        nl[a] = nlp[o];
+        kc[a] = kcp[o];
+        kf[a] = kfp[o];
+    }
+    const T hi = href ? href[i] + h[i] : h[i];
     T G[NE], qv[NE], S[NE + 1];
-    int ed[NE];
-    T div = 0, ksum = 0, run = 0, qlast = 0;
+    T div = 0, ksum = 0, run = 0;
     S[0] = 0;
 #pragma unroll
     for (int a = 0; a < NE; ++a) {
-        G[a] = 0;
-        qv[a] = 0;
-        ed[a] = 0;
+        const T ue = u[ed[a]];
+        const T hn = href ? href[nb[a]] + h[nb[a]] : h[nb[a]];
+        qv[a] = q[vx[a]];
+        G[a] = nl[a] * (T(0.5) * (hi + hn) * ue);
+        div += G[a];
+        ksum += kc[a] * ue * ue;
+        run += kf[a];
         S[a + 1] = run;
-        if (a < n) {
-            const size_t o = (size_t)a * nC + i;
-            const int e = m.eoc[o];
-            const T ue = u[e];
-            const T F = T(0.5) * (hi + h[m.coc[o]]) * ue;
-            G[a] = m.nl[o] * F;
-            div += G[a];
-            ksum += m.kc[o] * ue * ue;
-            qv[a] = q[m.voc[o]];
-            qlast = qv[a];
-            run += m.kf[o];
-            S[a + 1] = run;
-            ed[a] = e;
-        }
     }
-    const T phi = g * (hi + m.bot[i]) + ksum;
-    // q~ of edge a: mean of the vertices before (slot a-1) and after (slot a) it
+    const T phi = g * (h[i] + m.beta[i]) + ksum;
+    // q~ of edge a: mean of the vertices before (slot a-1) and after (slot a)
+    // it; the padding repeats the last vertex, so slot NE-1 holds slot n-1's.
     T qt[NE];
 #pragma unroll
-    for (int a = 0; a < NE; ++a) qt[a] = T(0.5) * ((a == 0 ? qlast : qv[a > 0 ? a - 1 : 0]) + qv[a]);
+    for (int a = 0; a < NE; ++a) qt[a] = T(0.5) * (qv[(a + NE - 1) % NE] + qv[a]);
     const size_t nE = (size_t)m.nE;
 #pragma unroll
     for (int b = 0; b < NE; ++b) {
-        if (b < n) {
-            T acc = 0;
+        T acc = 0;
 #pragma unroll
-            for (int a = 0; a < NE; ++a) {
-                if (a < n && a != b) {
-                    const T R = a < b ? S[b] - S[a] : (run - S[a]) + S[b];
-                    acc += (R - T(0.5)) * G[a] * (T(0.5) * (qt[b] + qt[a]));
-                }
+        for (int a = 0; a < NE; ++a) {
+            if (a != b) {
+                const T R = a < b ? S[b] - S[a] : (run - S[a]) + S[b];
+                acc += (R - T(0.5)) * G[a] * (T(0.5) * (qt[b] + qt[a]));
             }
+        }
+        if (b < n) {
             const T ndb = m.nd[(size_t)b * nC + i];
-            const int side = ndb > T(0) ? 0 : 1;
-            zs[side * nE + ed[b]] = ndb * (phi + acc);
+            zs[(ndb > T(0) ? 0 : nE) + ed[b]] = ndb * (phi + acc);
         }
     }
     const T H = -div / m.area[i];
@@ -138,51 +163,45 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restri
 }
 
 template <typename T>
+__device__ void run_aux(const Aux<T>& x, int j) {
+    if (x.kind == 1) {
+        if (j < x.nh)
+            x.xh[x.lo_h + j] = T(x.c0 * (double)x.ah[j] + x.c1 * (double)x.bh[j] +
+                                 x.c2 * (double)x.ch[j]);
+        else if (j < x.nh + x.nu) {
+            const int k = j - x.nh;
+            x.xu[x.lo_u + k] = T(x.c0 * (double)x.au[k] + x.c1 * (double)x.bu[k] +
+                                 x.c2 * (double)x.cu[k]);
+        }
+    } else if (x.kind == 2) {
+        const T d = (T)x.c0;
+        if (j < x.nh) {
+            const T base = j < x.nbh ? x.ah[j] : x.xh[x.lo_h + j];
+            x.xh[x.lo_h + j] = base + d * x.bh[j];
+        } else if (j < x.nh + x.nu) {
+            const int k = j - x.nh;
+            const T base = k < x.nbu ? x.au[k] : x.xu[x.lo_u + k];
+            x.xu[x.lo_u + k] = base + d * x.bu[k];
+        }
+    }
+}
+
+// Edge tendency U_e = Z_{c0}(e) + Z_{c1}(e) with its epilogue; blocks past the
+// edge range run the appended element-wise job.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_edge(const T* __restrict__ zs, int nE, int lo,
-                                                 int hi, Seg<T> s0, Seg<T> s1, int* flag) {
-    const int e = lo + blockIdx.x * kBlock + threadIdx.x;
+                                                 int hi, int nbe, Seg<T> s0, Seg<T> s1,
+                                                 Aux<T> aux, int* flag) {
+    if ((int)blockIdx.x >= nbe) {
+        run_aux(aux, (blockIdx.x - nbe) * kBlock + threadIdx.x);
+        return;
+    }
+    const int b = blockIdx.x, x = b & 7, k = b >> 3, qq = nbe >> 3, r = nbe & 7;
+    const int lb = x < r ? x * (qq + 1) + k : r * (qq + 1) + (x - r) * qq + k;
+    const int e = lo + lb * kBlock + threadIdx.x;
     if (e >= hi) return;
     const T U = zs[e] + zs[(size_t)nE + e];
     epilogue(e, U, s0, s1, flag);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_predict(T* xh, const T* ah, const T* bh,
-                                                    const T* ch, int lo_h, int nh, T* xu,
-                                                    const T* au, const T* bu, const T* cu,
-                                                    int lo_u, int nu, double c0, double c1,
-                                                    double c2) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j < nh) {
-        xh[lo_h + j] = T(c0 * (double)ah[j] + c1 * (double)bh[j] + c2 * (double)ch[j]);
-    } else if (j < nh + nu) {
-        const int k = j - nh;
-        xu[lo_u + k] = T(c0 * (double)au[k] + c1 * (double)bu[k] + c2 * (double)cu[k]);
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy(T* dh, const T* sh, int lo_h, int nh, T* du,
-                                                 const T* su, int lo_u, int nu) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j < nh) dh[j] = sh[lo_h + j];
-    else if (j < nh + nu) du[j - nh] = su[lo_u + j - nh];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_correct(T* xh, const T* baseh, const T* acch,
-                                                    int lo_h, int nh, int nbh, T* xu,
-                                                    const T* baseu, const T* accu, int lo_u,
-                                                    int nu, int nbu, T delta) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j < nh) {
-        const T b = j < nbh ? baseh[j] : xh[lo_h + j];
-        xh[lo_h + j] = b + delta * acch[j];
-    } else if (j < nh + nu) {
-        const int k = j - nh;
-        const T b = k < nbu ? baseu[k] : xu[lo_u + k];
-        xu[lo_u + k] = b + delta * accu[k];
-    }
 }
 
 // Diagnostics: block partials [mass, energy, -h_min, h_max, |u|max, nonfinite]
@@ -197,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_part(DevMesh<T> m, const T* __r
     if ((int)blockIdx.x < nblk_cells) {
         const int i = blockIdx.x * kBlock + t;
         if (i < m.nC) {
-            const double hi = (double)h[i];
+            const double hi = m.href ? (double)m.href[i] + (double)h[i] : (double)h[i];
             double K = 0.0;
             const int n = m.nEoC[i];
             for (int a = 0; a < n; ++a) {
@@ -276,69 +295,49 @@ inline unsigned nblocks(long n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 int diag_blocks(int n) { return (int)nblocks(n); }
 
+// Plain launch, or an event-stamped launch in timing mode.
+template <typename K, typename... Args>
+hipError_t launch(K kernel, dim3 grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                  Args... args) {
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, ev0, ev1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, args...);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_vertex(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo, int v_hi,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (v_hi <= v_lo) return hipSuccess;
-    hipLaunchKernelGGL(k_vertex<T>, dim3(nblocks(v_hi - v_lo)), dim3(kBlock), 0, s, m, h, u, q,
-                       v_lo, v_hi);
-    return hipGetLastError();
+    return launch(k_vertex<T>, dim3(nblocks(v_hi - v_lo)), s, ev0, ev1, m, h, u, q, v_lo, v_hi);
 }
 
 template <typename T>
 hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs, int c_lo,
                        int c_hi, T g, const Seg<T>& s0, const Seg<T>& s1, int* flag,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (c_hi <= c_lo) return hipSuccess;
     const dim3 grid(nblocks(c_hi - c_lo));
-    if (m.maxE <= 6)
-        hipLaunchKernelGGL((k_cell<T, 6>), grid, dim3(kBlock), 0, s, m, h, u, q, zs, c_lo, c_hi,
-                           g, s0, s1, flag);
-    else if (m.maxE <= 8)
-        hipLaunchKernelGGL((k_cell<T, 8>), grid, dim3(kBlock), 0, s, m, h, u, q, zs, c_lo, c_hi,
-                           g, s0, s1, flag);
-    else
-        hipLaunchKernelGGL((k_cell<T, LTS_MAX_EDGES>), grid, dim3(kBlock), 0, s, m, h, u, q, zs,
-                           c_lo, c_hi, g, s0, s1, flag);
-    return hipGetLastError();
+    const int ns = padded_slots(m.maxE);
+    if (ns == 6)
+        return launch(k_cell<T, 6>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
+    if (ns == 8)
+        return launch(k_cell<T, 8>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
+    return launch(k_cell<T, LTS_MAX_EDGES>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0,
+                  s1, flag);
 }
+
+int padded_slots(int maxE) { return maxE <= 6 ? 6 : maxE <= 8 ? 8 : LTS_MAX_EDGES; }
 
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, const Seg<T>& s1,
-                       int* flag, hipStream_t s) {
-    if (hi <= lo) return hipSuccess;
-    hipLaunchKernelGGL(k_edge<T>, dim3(nblocks(hi - lo)), dim3(kBlock), 0, s, zs, nE, lo, hi, s0,
-                       s1, flag);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_predict(T* xh, const T* ah, const T* bh, const T* ch, int lo_h, int nh, T* xu,
-                          const T* au, const T* bu, const T* cu, int lo_u, int nu, double c0,
-                          double c1, double c2, hipStream_t s) {
-    if (nh + nu <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_predict<T>, dim3(nblocks((long)nh + nu)), dim3(kBlock), 0, s, xh, ah,
-                       bh, ch, lo_h, nh, xu, au, bu, cu, lo_u, nu, c0, c1, c2);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_copy(T* dh, const T* sh, int lo_h, int nh, T* du, const T* su, int lo_u, int nu,
-                       hipStream_t s) {
-    if (nh + nu <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy<T>, dim3(nblocks((long)nh + nu)), dim3(kBlock), 0, s, dh, sh, lo_h,
-                       nh, du, su, lo_u, nu);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_correct(T* xh, const T* baseh, const T* acch, int lo_h, int nh, int nbh, T* xu,
-                          const T* baseu, const T* accu, int lo_u, int nu, int nbu, double delta,
-                          hipStream_t s) {
-    if (nh + nu <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_correct<T>, dim3(nblocks((long)nh + nu)), dim3(kBlock), 0, s, xh, baseh,
-                       acch, lo_h, nh, nbh, xu, baseu, accu, lo_u, nu, nbu, (T)delta);
-    return hipGetLastError();
+                       const Aux<T>& aux, int* flag, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+    const int nbe = hi > lo ? (int)nblocks(hi - lo) : 0;
+    const int nba = aux.kind ? (int)nblocks((long)aux.nh + aux.nu) : 0;
+    if (nbe + nba == 0) return hipSuccess;
+    return launch(k_edge<T>, dim3(nbe + nba), s, ev0, ev1, zs, nE, lo, hi, nbe, s0, s1, aux, flag);
 }
 
 template <typename T>
@@ -360,18 +359,12 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
 
 #define LTS_INSTANTIATE(T)                                                                      \
     template hipError_t launch_vertex<T>(const DevMesh<T>&, const T*, const T*, T*, int, int,    \
-                                         hipStream_t);                                          \
+                                         hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_cell<T>(const DevMesh<T>&, const T*, const T*, const T*, T*, int, \
-                                       int, T, const Seg<T>&, const Seg<T>&, int*, hipStream_t); \
+                                       int, T, const Seg<T>&, const Seg<T>&, int*, hipStream_t,  \
+                                       hipEvent_t, hipEvent_t);                                 \
     template hipError_t launch_edge<T>(const T*, int, int, int, const Seg<T>&, const Seg<T>&,    \
-                                       int*, hipStream_t);                                      \
-    template hipError_t launch_predict<T>(T*, const T*, const T*, const T*, int, int, T*,        \
-                                          const T*, const T*, const T*, int, int, double,       \
-                                          double, double, hipStream_t);                         \
-    template hipError_t launch_copy<T>(T*, const T*, int, int, T*, const T*, int, int,           \
-                                       hipStream_t);                                            \
-    template hipError_t launch_correct<T>(T*, const T*, const T*, int, int, int, T*, const T*,   \
-                                          const T*, int, int, int, double, hipStream_t);        \
+                                       const Aux<T>&, int*, hipStream_t, hipEvent_t, hipEvent_t);\
     template hipError_t launch_diag<T>(const DevMesh<T>&, const T*, const T*, double, double*,   \
                                        int, int, double*, hipStream_t);
 

@@ -277,3 +277,43 @@ def jittered_hex_points(nx, ny, dc, jitter, seed):
     p[:, 0] %= Lx
     p[:, 1] %= Ly
     return p, Lx, Ly
+
+
+# ---------------------------------------------------------------------------
+# The variable-resolution planar workload
+
+VR_DOMAIN = 2.0e6          # doubly periodic 2000 km x 2000 km
+VR_RADIUS = 1.5e5          # fine disk radius 150 km
+VR_WIDTH = 5.0e4           # tanh transition width 50 km
+VR_RATIO = 8.0             # dc_out / dc_in (2 km inside, 16 km outside)
+
+
+def vr_spacing_shape(x, y):
+    """Relative target spacing (1 inside the disk, 8 outside, tanh blend)."""
+    d = np.hypot(x - VR_DOMAIN / 2, y - VR_DOMAIN / 2)
+    return tanh_spacing(d, 1.0, VR_RATIO, VR_RADIUS, VR_WIDTH)
+
+
+def vr_points(n: int, seed: int, iters: int, progress=None):
+    """Seeded points Lloyd-relaxed under density rho ~ spacing^-4."""
+    L = VR_DOMAIN
+    p = sample_points(n, L, L, vr_spacing_shape, seed)
+    dens = lambda x, y: vr_spacing_shape(x, y) ** -4.0
+    for it in range(iters):
+        p = lloyd_step(p, L, L, dens)
+        if progress:
+            progress(it)
+    return p
+
+
+def morton_sort(points, L):
+    q = np.clip((points / L * 65535.0).astype(np.int64), 0, 65535)
+
+    def spread(v):
+        v = (v | (v << 8)) & 0x00FF00FF
+        v = (v | (v << 4)) & 0x0F0F0F0F
+        v = (v | (v << 2)) & 0x33333333
+        v = (v | (v << 1)) & 0x55555555
+        return v
+    key = spread(q[:, 0]) | (spread(q[:, 1]) << 1)
+    return points[np.argsort(key, kind="stable")]

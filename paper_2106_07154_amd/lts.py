@@ -19,8 +19,7 @@ LTS_OK, LTS_EINVAL, LTS_EMESH, LTS_ELABEL, LTS_ENONFINITE, LTS_EDEVICE, LTS_ESTA
     0, -1, -2, -3, -4, -5, -6, -7
 LTS_FP64, LTS_FP32 = 0, 1
 LTS_C, LTS_I2, LTS_I1, LTS_F = 0, 1, 2, 3
-KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency", "interface_predict",
-                  "interface_correct", "copy", "diagnostics"]
+KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency"]
 
 EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
             "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_eval_rhs",
@@ -116,6 +115,11 @@ class LTSContext:
         self._lib = load_library()
         self.precision = precision
         prec = {"fp64": LTS_FP64, "fp32": LTS_FP32}[precision]
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream  # a torch.cuda.Stream
+        if stream == 0:
+            raise ValueError("pass a non-default stream (handle 0 is the legacy null stream); "
+                             "None makes the context create its own")
         h = ctypes.c_void_p()
         st = self._lib.lts_create(ctypes.byref(h), int(device), prec,
                                   ctypes.c_void_p(stream) if stream else None)

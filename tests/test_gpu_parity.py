@@ -284,3 +284,15 @@ def test_lts3_fp32_parity(igw):
         rel_l2(h - 1000.0, rh - 1000.0, m.areaCell))
     assert eh < 1e-5 and eu < 1e-5
     c.close()
+
+
+def test_rhs_parity_fp32(request):
+    for name, m, fm in _cases(request):
+        say("rhs fp32", name)
+        c = make_ctx(m, fm, prec="fp32")
+        h, u = random_state(m, 4, H=1000.0, amp_h=3.0, amp_u=1.0)
+        c.init_state(h, u)  # sets the thickness reference of the perturbation form
+        dh, du = c.eval_rhs(h, u)
+        rh, ru = Oracle(m).rhs(h, u)
+        assert rel_l2(dh, rh) < 1e-5 and rel_l2(du, ru) < 1e-5, name
+        c.close()

@@ -350,7 +350,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
         area[ni] = m->area_cell[i];
         bot[ni] = m->bottom[i];
         for (int j = 0; j < n; ++j) {
-            const size_t o = (size_t)j * nC + ni;
+            const size_t o = (size_t)ni * mx + j;
             const int e = m->edges_on_cell[(size_t)i * m->max_edges + j];
             const int v = m->vertices_on_cell[(size_t)i * m->max_edges + j];
             eoc[o] = einv[e];
@@ -367,7 +367,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
         }
         // padding slots: repeat the last real slot's indices, zero coefficients
         for (int j = n; j < mx; ++j) {
-            const size_t o = (size_t)j * nC + ni, ol = (size_t)(n - 1) * nC + ni;
+            const size_t o = (size_t)ni * mx + j, ol = (size_t)ni * mx + n - 1;
             eoc[o] = eoc[ol];
             coc[o] = coc[ol];
             voc[o] = voc[ol];

@@ -9,20 +9,21 @@
 
 namespace lts {
 
-// Device mesh in structure-of-arrays form, permuted so that every LTS region
-// is a contiguous range.  Per-cell slot tables are slot-major ([slot][cell]) so
-// that a wavefront reading slot j of 64 consecutive cells is coalesced.
+// Device mesh, permuted so that every LTS region is a contiguous range.
+// Per-cell slot tables are cell-major with G = padded_slots(maxE) slots per
+// cell ([cell][G]): the cell kernel gives each slot its own lane, so a
+// wavefront reads 64 consecutive table entries.
 template <typename T>
 struct DevMesh {
     int nC, nE, nV, maxE;
     const int32_t* nEoC;   // [nC]
-    const int32_t* eoc;    // [maxE][nC] edge of slot j (ccw)
-    const int32_t* coc;    // [maxE][nC] cell across edge j
-    const int32_t* voc;    // [maxE][nC] vertex between edge j and j+1
-    const T* nl;           // [maxE][nC] n_{e,i} l_e
-    const T* nd;           // [maxE][nC] n_{e,i} / d_e
-    const T* kc;           // [maxE][nC] l_e d_e / (4 A_i)
-    const T* kf;           // [maxE][nC] A_{i,v_j} / A_i (kite fraction of vertex slot j)
+    const int32_t* eoc;    // [nC][G] edge of slot j (ccw)
+    const int32_t* coc;    // [nC][G] cell across edge j
+    const int32_t* voc;    // [nC][G] vertex between edge j and j+1
+    const T* nl;           // [nC][G] n_{e,i} l_e
+    const T* nd;           // [nC][G] n_{e,i} / d_e
+    const T* kc;           // [nC][G] l_e d_e / (4 A_i)
+    const T* kf;           // [nC][G] A_{i,v_j} / A_i (kite fraction of vertex slot j)
     const T* area;         // [nC] A_i
     const T* bot;          // [nC] b_i (diagnostics)
     // Thickness storage.  href == nullptr: the state holds h itself and
@@ -93,8 +94,8 @@ template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0,
                        const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-// Number of cell slots the device tables are padded to for a mesh with maxE.
-int padded_slots(int maxE);
+// Slots per cell in the device tables (and lanes per cell in the cell kernel).
+__host__ __device__ inline int padded_slots(int maxE) { return maxE <= 8 ? 8 : 16; }
 // Diagnostics partials per block (mass, energy, h_min, h_max, |u|max, nonfinite)
 // then a single-block deterministic reduction into out[8] (doubles).
 template <typename T>

@@ -89,77 +89,73 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __rest
     q[v] = (m.fA[v] + circ) / hv;
 }
 
-// Slots n..NE-1 of every cell are padding: valid indices (copies of slot
-// n-1) and zero coefficients, so the kernel runs without per-slot branches and
-// issues every gather of a cell up front.
-template <typename T, int NE>
+// Cell kernel: one lane per edge slot, G lanes per cell (G = 8 or 16), so a
+// wave64 covers 64/G cells and every slot's gathers are issued by its own
+// lane.  Slot tables are cell-major ([cell][G]); slots n..G-1 are padding with
+// valid indices (copies of slot n-1) and zero coefficients.
+//
+// The PV part of Z_i(b) is rewritten with prefix sums: with S_a the kite
+// fractions summed counter-clockwise before slot a and S_n their total,
+//   R_ab - 1/2 = (S_b - 1/2) - S_a + S_n [a > b],
+// so for any slot quantity X
+//   sum_{a != b} (R_ab - 1/2) X_a = (S_b - 1/2)(sum X - X_b)
+//                                   - (sum S X - S_b X_b) + S_n sum_{a > b} X_a,
+// and the PV sum is (1/2) q~_b P_b(G) + (1/2) P_b(G q~).  Group sums and scans
+// use cross-lane shuffles within the G lanes of a cell.
+template <typename T, int G>
+__device__ __forceinline__ T gsum(T x) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) x += __shfl_xor(x, d, G);
+    return x;
+}
+template <typename T, int G>
+__device__ __forceinline__ T gscan(T x, int lane) {  // inclusive
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const T y = __shfl_up(x, d, G);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
                                                  int* flag) {
-    const int i = c_lo + xcd_block() * kBlock + threadIdx.x;
-    if (i >= c_hi) return;
-    const int nC = m.nC;
-    const int32_t* __restrict__ eoc = m.eoc;
-    const int32_t* __restrict__ coc = m.coc;
-    const int32_t* __restrict__ voc = m.voc;
-    const T* __restrict__ nlp = m.nl;
-    const T* __restrict__ kcp = m.kc;
-    const T* __restrict__ kfp = m.kf;
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int lane = t & (G - 1);
+    const int ic = c_lo + t / G;
+    const bool live = ic < c_hi;
+    const int i = live ? ic : c_hi - 1;  // dead lanes shadow a valid cell
     const T* __restrict__ href = m.href;
+    const size_t o = (size_t)i * G + lane;
+    const int e = m.eoc[o];
+    const int nb = m.coc[o];
+    const int v = m.voc[o];
+    const T nl = m.nl[o], kc = m.kc[o], kf = m.kf[o], nd = m.nd[o];
     const int n = m.nEoC[i];
-    int ed[NE], nb[NE], vx[NE];
-    T nl[NE], kc[NE], kf[NE];
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-        const size_t o = (size_t)a * nC + i;
-        ed[a] = eoc[o];
-        nb[a] = coc[o];
-        vx[a] = voc[o];
-        nl[a] = nlp[o];
-        kc[a] = kcp[o];
-        kf[a] = kfp[o];
-    }
     const T hi = href ? href[i] + h[i] : h[i];
-    T G[NE], qv[NE], S[NE + 1];
-    T div = 0, ksum = 0, run = 0;
-    S[0] = 0;
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-        const T ue = u[ed[a]];
-        const T hn = href ? href[nb[a]] + h[nb[a]] : h[nb[a]];
-        qv[a] = q[vx[a]];
-        G[a] = nl[a] * (T(0.5) * (hi + hn) * ue);
-        div += G[a];
-        ksum += kc[a] * ue * ue;
-        run += kf[a];
-        S[a + 1] = run;
-    }
-    const T phi = g * (h[i] + m.beta[i]) + ksum;
-    // q~ of edge a: mean of the vertices before (slot a-1) and after (slot a)
-    // it; the padding repeats the last vertex, so slot NE-1 holds slot n-1's.
-    T qt[NE];
-#pragma unroll
-    for (int a = 0; a < NE; ++a) qt[a] = T(0.5) * (qv[(a + NE - 1) % NE] + qv[a]);
-    const size_t nE = (size_t)m.nE;
-#pragma unroll
-    for (int b = 0; b < NE; ++b) {
-        T acc = 0;
-#pragma unroll
-        for (int a = 0; a < NE; ++a) {
-            if (a != b) {
-                const T R = a < b ? S[b] - S[a] : (run - S[a]) + S[b];
-                acc += (R - T(0.5)) * G[a] * (T(0.5) * (qt[b] + qt[a]));
-            }
-        }
-        if (b < n) {
-            const T ndb = m.nd[(size_t)b * nC + i];
-            zs[(ndb > T(0) ? 0 : nE) + ed[b]] = ndb * (phi + acc);
-        }
-    }
-    const T H = -div / m.area[i];
-    epilogue(i, H, s0, s1, flag);
+    const T hn = href ? href[nb] + h[nb] : h[nb];
+    const T ue = u[e];
+    const T qv = q[v];
+    const T Ga = nl * (T(0.5) * (hi + hn) * ue);
+    const T K = gsum<T, G>(kc * ue * ue);
+    const T Sinc = gscan<T, G>(kf, lane);
+    const T Sb = Sinc - kf;                      // S_b: fractions before slot b
+    const T Sn = __shfl(Sinc, G - 1, G);         // S_n
+    const T qt = T(0.5) * (__shfl(qv, (lane + G - 1) & (G - 1), G) + qv);
+    const T X1 = Ga, X2 = Ga * qt;
+    const T c1 = gscan<T, G>(X1, lane), c2 = gscan<T, G>(X2, lane);
+    const T t1 = __shfl(c1, G - 1, G), t2 = __shfl(c2, G - 1, G);  // sums; t1 = sum G
+    const T p1 = gsum<T, G>(Sb * X1), p2 = gsum<T, G>(Sb * X2);
+    const T P1 = (Sb - T(0.5)) * (t1 - X1) - (p1 - Sb * X1) + Sn * (t1 - c1);
+    const T P2 = (Sb - T(0.5)) * (t2 - X2) - (p2 - Sb * X2) + Sn * (t2 - c2);
+    const T phi = g * (h[i] + m.beta[i]) + K;
+    if (live && lane < n)
+        zs[(nd > T(0) ? 0 : (size_t)m.nE) + e] = nd * (phi + T(0.5) * qt * P1 + T(0.5) * P2);
+    if (live && lane == 0) epilogue(i, -t1 / m.area[i], s0, s1, flag);
 }
 
 template <typename T>
@@ -219,8 +215,9 @@ __global__ __launch_bounds__(kBlock) void k_diag_part(DevMesh<T> m, const T* __r
             const double hi = m.href ? (double)m.href[i] + (double)h[i] : (double)h[i];
             double K = 0.0;
             const int n = m.nEoC[i];
+            const int G = padded_slots(m.maxE);
             for (int a = 0; a < n; ++a) {
-                const size_t o = (size_t)a * m.nC + i;
+                const size_t o = (size_t)i * G + a;
                 const double ue = (double)u[m.eoc[o]];
                 K += (double)m.kc[o] * ue * ue;
             }
@@ -318,17 +315,12 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
                        int c_hi, T g, const Seg<T>& s0, const Seg<T>& s1, int* flag,
                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (c_hi <= c_lo) return hipSuccess;
-    const dim3 grid(nblocks(c_hi - c_lo));
-    const int ns = padded_slots(m.maxE);
-    if (ns == 6)
-        return launch(k_cell<T, 6>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
-    if (ns == 8)
+    const int G = padded_slots(m.maxE);
+    const dim3 grid(nblocks((long)(c_hi - c_lo) * G));
+    if (G == 8)
         return launch(k_cell<T, 8>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
-    return launch(k_cell<T, LTS_MAX_EDGES>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0,
-                  s1, flag);
+    return launch(k_cell<T, 16>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
 }
-
-int padded_slots(int maxE) { return maxE <= 6 ? 6 : maxE <= 8 ? 8 : LTS_MAX_EDGES; }
 
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, const Seg<T>& s1,

@@ -126,6 +126,19 @@ lts_status lts_step(lts_ctx *ctx, double dt_coarse, int M, int n_steps);
    whole mesh; an independent code path from lts_step. */
 lts_status lts_step_rk3(lts_ctx *ctx, double dt, int n_steps);
 
+/* Time integration schemes of lts_step_scheme. */
+typedef enum {
+    LTS_SCHEME_LTS3 = 0,   /* Algorithm 2.2, third-order branch (= lts_step)      */
+    LTS_SCHEME_LTS2 = 1,   /* Algorithm 2.2, second-order branch                  */
+    LTS_SCHEME_SSPRK3 = 2, /* Algorithm 2.1, three stages (= lts_step_rk3)        */
+    LTS_SCHEME_SSPRK2 = 3, /* Algorithm 2.1, two stages                           */
+    LTS_SCHEME_RK4 = 4     /* classical RK4, the paper's reference and competitor */
+} lts_scheme;
+
+/* Advance n_steps steps of `scheme` with step dt (the coarse step for LTS2/3,
+   fine step dt/M; M is ignored by the global schemes).  Asynchronous. */
+lts_status lts_step_scheme(lts_ctx *ctx, int scheme, double dt, int M, int n_steps);
+
 /* Evaluate the right-hand side (H, U) of eq:sweTimeStepping at the given host
    state (caller numbering) over the whole mesh.  Does not change the state. */
 lts_status lts_eval_rhs(lts_ctx *ctx, const double *h, const double *u,

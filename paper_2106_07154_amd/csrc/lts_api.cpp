@@ -83,6 +83,7 @@ struct lts_ctx {
     void *x0h = nullptr, *x1h = nullptr, *x2h = nullptr, *x0u = nullptr, *x1u = nullptr,
          *x2u = nullptr;
     void *acch = nullptr, *accu = nullptr, *zs = nullptr, *q = nullptr;
+    void *Qh = nullptr, *Qu = nullptr;  // RK4 stage sums (allocated on first use)
     int* flag = nullptr;
     double *dpart = nullptr, *dout = nullptr;
 
@@ -95,7 +96,7 @@ struct lts_ctx {
     std::vector<double> bot_perm, area_perm; // device order
     void *d_href = nullptr, *d_beta = nullptr;
 
-    // graph cache for one coarse step
+    // graph cache for one step of one scheme
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int g_kind = -1, g_M = 0;
@@ -141,6 +142,7 @@ void free_device(lts_ctx* c) {
     c->g_kind = -1;
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
+    c->Qh = c->Qu = nullptr;
     if (c->dm) {
         if (c->prec == LTS_FP64) delete static_cast<DevMesh<double>*>(c->dm);
         else delete static_cast<DevMesh<float>*>(c->dm);
@@ -454,6 +456,12 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     for (void* b : {c->Ah, c->Bh, c->Ch}) HIPCHK(c, hipMemset(b, 0, nC * ts));
     for (void* b : {c->Au, c->Bu, c->Cu}) HIPCHK(c, hipMemset(b, 0, nE * ts));
     HIPCHK(c, hipMemset(c->zs, 0, 2 * (size_t)nE * ts));
+    // interface copies hold n_I1 elements, accumulators n_I1 + n_I2 (each
+    // allocation is at least 8 bytes)
+    for (void* b : {c->x0h, c->x1h, c->x2h}) HIPCHK(c, hipMemset(b, 0, nI1c * ts));
+    for (void* b : {c->x0u, c->x1u, c->x2u}) HIPCHK(c, hipMemset(b, 0, nI1e * ts));
+    HIPCHK(c, hipMemset(c->acch, 0, nIc * ts));
+    HIPCHK(c, hipMemset(c->accu, 0, nIe * ts));
     HIPCHK(c, hipMemset(c->q, 0, nV * ts));
     HIPCHK(c, hipMemset(c->flag, 0, 64));
     HIPCHK(c, hipDeviceSynchronize());
@@ -616,10 +624,10 @@ struct Run {
         g.mcur = mcur;
         return g;
     }
-    Aux<T> predict_aux(T* xh, T* xu, int stage, int k, int M) {
+    Aux<T> predict_aux(T* xh, T* xu, int stage, int k, int M, int order = 3) {
         Aux<T> x;
         double cf[3];
-        predict_coeffs(stage, k, M, cf);
+        predict_coeffs(stage, k, M, cf, order);
         x.kind = 1;
         x.nh = c->cb[4] - c->cb[3];
         x.nu = c->eb[3] - c->eb[2];
@@ -742,17 +750,101 @@ struct Run {
                     none, upd(0, nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none);
     }
 
+    // Algorithm 2.1, SSPRK2, over the whole mesh.
+    lts_status ssprk2_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        if ((st = pass(P_FULL, Ah, Au, upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), none,
+                       upd(0, nE, Bu, nullptr, 0, Au, 1, dt), none)))
+            return st;
+        return pass(P_FULL, Bh, Bu, upd(0, nC, Ah, Ah, 0.5, Bh, 0.5, 0.5 * dt), none,
+                    upd(0, nE, Au, Au, 0.5, Bu, 0.5, 0.5 * dt), none);
+    }
+
+    // Classical RK4 over the whole mesh: the stage sum k1 + 2 k2 + 2 k3 is
+    // accumulated in Q by the stage epilogues, the last stage adds dt/6 (Q + k4).
+    lts_status rk4_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu, *Qh = (T*)c->Qh, *Qu = (T*)c->Qu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        auto with_acc = [](Seg<T> g, T* acc, double theta, bool first) {
+            g.acc = acc;
+            g.theta = (T)theta;
+            g.first = first ? 1 : 0;
+            return g;
+        };
+        if ((st = pass(P_FULL, Ah, Au,
+                       with_acc(upd(0, nC, Bh, nullptr, 0, Ah, 1, 0.5 * dt), Qh, 1.0, true), none,
+                       with_acc(upd(0, nE, Bu, nullptr, 0, Au, 1, 0.5 * dt), Qu, 1.0, true), none)))
+            return st;
+        if ((st = pass(P_FULL, Bh, Bu,
+                       with_acc(upd(0, nC, Ch, nullptr, 0, Ah, 1, 0.5 * dt), Qh, 2.0, false), none,
+                       with_acc(upd(0, nE, Cu, nullptr, 0, Au, 1, 0.5 * dt), Qu, 2.0, false), none)))
+            return st;
+        if ((st = pass(P_FULL, Ch, Cu,
+                       with_acc(upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), Qh, 2.0, false), none,
+                       with_acc(upd(0, nE, Bu, nullptr, 0, Au, 1, dt), Qu, 2.0, false), none)))
+            return st;
+        return pass(P_FULL, Bh, Bu, upd(0, nC, Ah, Ah, 1.0, Qh, dt / 6.0, dt / 6.0), none,
+                    upd(0, nE, Au, Au, 1.0, Qu, dt / 6.0, dt / 6.0), none);
+    }
+
+    // Algorithm 2.2, order 2 (LTS2).  Step 2 (the coarse second stage on C)
+    // reads only X0 and X1, and nothing in Step 3 reads its result, so it runs
+    // after the substeps, writing the new coarse values straight into A with
+    // the interface correction riding on its edge kernel.
+    lts_status lts2_step(double dt, int M) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu;
+        const int* cb = c->cb;
+        const int* eb = c->eb;
+        const int nC = c->nC, nE = c->nE;
+        const double delta = dt / M;
+        const Seg<T> none;
+        lts_status st;
+        // Step 1: first stage with dt on I1, I2, C
+        if ((st = pass(P_STEP2, Ah, Au,
+                       mirror(upd(cb[3], nC, Bh, nullptr, 0, Ah, 1, dt), cb[3], cb[4],
+                              (T*)c->x1h, (T*)c->x0h),
+                       none,
+                       mirror(upd(eb[2], nE, Bu, nullptr, 0, Au, 1, dt), eb[2], eb[3],
+                              (T*)c->x1u, (T*)c->x0u),
+                       none)))
+            return st;
+        for (int k = 0; k < M; ++k) {
+            if ((st = pass(P_STEP3, Ah, Au, upd(0, cb[3], Bh, nullptr, 0, Ah, 1, delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 0.5, k == 0),
+                           upd(0, eb[2], Bu, nullptr, 0, Au, 1, delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 0.5, k == 0),
+                           predict_aux(Bh, Bu, 1, k, M, 2))))
+                return st;
+            if ((st = pass(P_STEP3, Bh, Bu,
+                           upd(0, cb[3], Ah, Ah, 0.5, Bh, 0.5, 0.5 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 0.5, false),
+                           upd(0, eb[2], Au, Au, 0.5, Bu, 0.5, 0.5 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 0.5, false),
+                           k + 1 < M ? predict_aux(Ah, Au, 0, k + 1, M, 2) : Aux<T>())))
+                return st;
+        }
+        // Step 2 on C: new = 1/2 X0 + 1/2 X1 + 1/2 dt R(X1), into A; Step 5 rides along
+        return pass(P_STEP4, Bh, Bu, upd(cb[5], nC, Ah, Ah, 0.5, Bh, 0.5, 0.5 * dt), none,
+                    upd(eb[4], nE, Au, Au, 0.5, Bu, 0.5, 0.5 * dt), none, correct_aux(delta));
+    }
+
     // Interface-1 prediction coefficients of Algorithm 2.2 (Steps 3.1.1,
-    // 3.2.1, 3.3.1), in FP64: (1 - a - a~, a - a~, 2 a~).
-    static void predict_coeffs(int stage, int k, int M, double out[3]) {
+    // 3.2.1, 3.3.1), in FP64: (1 - a - a~, a - a~, 2 a~); a~ = 0 for LTS2.
+    static void predict_coeffs(int stage, int k, int M, double out[3], int order = 3) {
         const double dk = k, dM = M;
         double a, at;
         if (stage == 0) {
             a = dk / dM;
-            at = (dk * dk) / (dM * dM);
+            at = order == 3 ? (dk * dk) / (dM * dM) : 0.0;
         } else if (stage == 1) {
             a = (dk + 1.0) / dM;
-            at = dk * (dk + 2.0) / (dM * dM);
+            at = order == 3 ? dk * (dk + 2.0) / (dM * dM) : 0.0;
         } else {
             a = (2.0 * dk + 1.0) / (2.0 * dM);
             at = (2.0 * dk * dk + 2.0 * dk + 1.0) / (2.0 * dM * dM);
@@ -763,61 +855,40 @@ struct Run {
     }
 };
 
-template <typename T>
-lts_status run_lts(lts_ctx* c, double dt, int M, int n) {
-    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
-    Run<T> r{c, dm, c->stream, c->timing};
-    if (c->timing) {
-        for (int i = 0; i < n; ++i) {
-            lts_status st = r.lts3_step(dt, M);
-            if (st) return st;
-        }
-        return LTS_OK;
-    }
-    if (!(c->gexec && c->g_kind == 0 && c->g_M == M && c->g_dt == dt)) {
-        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-        if (c->graph) (void)hipGraphDestroy(c->graph);
-        c->gexec = nullptr;
-        c->graph = nullptr;
-        c->g_kind = -1;
-        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        lts_status st = r.lts3_step(dt, M);
-        hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(c->stream, &gr);
-        if (st) {
-            if (gr) (void)hipGraphDestroy(gr);
-            return st;
-        }
-        if (e != hipSuccess) return fail(c, LTS_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
-        c->graph = gr;
-        HIPCHK(c, hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
-        c->g_kind = 0;
-        c->g_M = M;
-        c->g_dt = dt;
-    }
-    for (int i = 0; i < n; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-    return LTS_OK;
-}
+enum { SCH_LTS3 = 0, SCH_LTS2 = 1, SCH_SSPRK3 = 2, SCH_SSPRK2 = 3, SCH_RK4 = 4 };
 
 template <typename T>
-lts_status run_rk3(lts_ctx* c, double dt, int n) {
+lts_status one_step(Run<T>& r, int scheme, double dt, int M) {
+    switch (scheme) {
+        case SCH_LTS3: return r.lts3_step(dt, M);
+        case SCH_LTS2: return r.lts2_step(dt, M);
+        case SCH_SSPRK3: return r.rk3_step(dt);
+        case SCH_SSPRK2: return r.ssprk2_step(dt);
+        default: return r.rk4_step(dt);
+    }
+}
+
+// Enqueue n steps of `scheme`: replayed from a hipGraph captured once per
+// (scheme, M, dt), or launched directly with event stamps in timing mode.
+template <typename T>
+lts_status run_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
     Run<T> r{c, dm, c->stream, c->timing};
     if (c->timing) {
         for (int i = 0; i < n; ++i) {
-            lts_status st = r.rk3_step(dt);
+            lts_status st = one_step<T>(r, scheme, dt, M);
             if (st) return st;
         }
         return LTS_OK;
     }
-    if (!(c->gexec && c->g_kind == 1 && c->g_dt == dt)) {
+    if (!(c->gexec && c->g_kind == scheme && c->g_M == M && c->g_dt == dt)) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         c->gexec = nullptr;
         c->graph = nullptr;
         c->g_kind = -1;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        lts_status st = r.rk3_step(dt);
+        lts_status st = one_step<T>(r, scheme, dt, M);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &gr);
         if (st) {
@@ -827,8 +898,8 @@ lts_status run_rk3(lts_ctx* c, double dt, int n) {
         if (e != hipSuccess) return fail(c, LTS_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
         c->graph = gr;
         HIPCHK(c, hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
-        c->g_kind = 1;
-        c->g_M = 0;
+        c->g_kind = scheme;
+        c->g_M = M;
         c->g_dt = dt;
     }
     for (int i = 0; i < n; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
@@ -1166,30 +1237,34 @@ lts_status lts_init_state_device(lts_ctx* c, const void* dh, const void* du, dou
     return lts_init_state(c, h.data(), u.data(), t0);
 }
 
-lts_status lts_step(lts_ctx* c, double dt, int M, int n) {
+lts_status lts_step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     lts_status s = ready(c, true);
     if (s) return s;
+    if (scheme < SCH_LTS3 || scheme > SCH_RK4) return fail(c, LTS_EINVAL, "unknown scheme");
+    if (scheme >= SCH_SSPRK3) M = 1;
     if (!(dt > 0) || M < 1 || n < 0) return fail(c, LTS_EINVAL, "need dt > 0, M >= 1, n >= 0");
     if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
     if (n == 0) return LTS_OK;
-    s = c->prec == LTS_FP64 ? run_lts<double>(c, dt, M, n) : run_lts<float>(c, dt, M, n);
+    if (scheme == SCH_RK4 && !c->Qh) {
+        const size_t ts = tsize(c);
+        if ((s = dalloc(c, &c->Qh, c->nC * ts)) || (s = dalloc(c, &c->Qu, c->nE * ts))) return s;
+        HIPCHK(c, hipMemset(c->Qh, 0, c->nC * ts));
+        HIPCHK(c, hipMemset(c->Qu, 0, c->nE * ts));
+    }
+    s = c->prec == LTS_FP64 ? run_scheme<double>(c, scheme, dt, M, n)
+                            : run_scheme<float>(c, scheme, dt, M, n);
     if (s) return s;
     c->t += dt * n;
     c->steps += n;
     return LTS_OK;
 }
 
+lts_status lts_step(lts_ctx* c, double dt, int M, int n) {
+    return lts_step_scheme(c, SCH_LTS3, dt, M, n);
+}
+
 lts_status lts_step_rk3(lts_ctx* c, double dt, int n) {
-    lts_status s = ready(c, true);
-    if (s) return s;
-    if (!(dt > 0) || n < 0) return fail(c, LTS_EINVAL, "need dt > 0, n >= 0");
-    if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
-    if (n == 0) return LTS_OK;
-    s = c->prec == LTS_FP64 ? run_rk3<double>(c, dt, n) : run_rk3<float>(c, dt, n);
-    if (s) return s;
-    c->t += dt * n;
-    c->steps += n;
-    return LTS_OK;
+    return lts_step_scheme(c, SCH_SSPRK3, dt, 1, n);
 }
 
 lts_status lts_eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, double* du) {

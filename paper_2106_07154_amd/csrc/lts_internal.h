@@ -42,6 +42,8 @@ struct DevMesh {
 // One epilogue segment: targets [lo, hi) of a tendency kernel.
 //   mode 1 (update):     out[j] = a_old*xold[j] + a_cur*xcur[j] + a_dt*G
 //   mode 2 (accumulate): acc[j-lo] = (first ? 0 : acc[j-lo]) + theta*G
+//   mode 1 with acc != nullptr also accumulates theta*G into acc (the RK4
+//   stage sum).
 //   mirror (update only): for j in [mlo, mhi) also store the new value to
 //   mnew[j-mlo] and the current value xcur[j] to mcur[j-mlo] (either may be
 //   null) -- the interface-1 copies of the coarse stages.

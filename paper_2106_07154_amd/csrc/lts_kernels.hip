@@ -55,6 +55,11 @@ __device__ __forceinline__ void apply_seg(int j, T G, const Seg<T>& s, int* flag
             if (s.mnew) s.mnew[j - s.mlo] = v;
             if (s.mcur) s.mcur[j - s.mlo] = s.xcur[j];
         }
+        if (s.acc) {
+            const int k = j - s.lo;
+            const T a = s.theta * G;
+            s.acc[k] = s.first ? a : s.acc[k] + a;
+        }
     } else {
         const int k = j - s.lo;
         v = s.theta * G;

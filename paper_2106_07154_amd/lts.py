@@ -22,7 +22,7 @@ LTS_C, LTS_I2, LTS_I1, LTS_F = 0, 1, 2, 3
 KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency"]
 
 EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
-            "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_eval_rhs",
+            "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_step_scheme", "lts_eval_rhs",
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy"]
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "lts_init_state_device": ([P, P, P, cd], ci),
         "lts_step": ([P, cd, ci, ci], ci),
         "lts_step_rk3": ([P, cd, ci], ci),
+        "lts_step_scheme": ([P, ci, cd, ci, ci], ci),
         "lts_eval_rhs": ([P, P, P, P, P], ci),
         "lts_diagnostics": ([P, ctypes.POINTER(_Diag)], ci),
         "lts_get_state": ([P, P, P], ci),
@@ -195,6 +196,12 @@ class LTSContext:
 
     def step_rk3(self, dt: float, n_steps: int = 1):
         self._check(self._lib.lts_step_rk3(self._h, float(dt), int(n_steps)))
+
+    SCHEMES = {"lts3": 0, "lts2": 1, "ssprk3": 2, "ssprk2": 3, "rk4": 4}
+
+    def step_scheme(self, scheme: str, dt: float, M: int = 1, n_steps: int = 1):
+        self._check(self._lib.lts_step_scheme(self._h, self.SCHEMES[scheme], float(dt), int(M),
+                                              int(n_steps)))
 
     def eval_rhs(self, h, u):
         h = np.ascontiguousarray(h, np.float64)

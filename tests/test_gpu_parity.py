@@ -296,3 +296,31 @@ def test_rhs_parity_fp32(request):
         rh, ru = Oracle(m).rhs(h, u)
         assert rel_l2(dh, rh) < 1e-5 and rel_l2(du, ru) < 1e-5, name
         c.close()
+
+
+@pytest.mark.parametrize("scheme,M,n", [("lts2", 4, 20), ("lts2", 1, 10), ("ssprk2", 1, 10),
+                                        ("rk4", 1, 20), ("lts3", 4, 10)])
+def test_scheme_parity(igw, scheme, M, n):
+    """Every scheme of lts_step_scheme against the oracle's implementation."""
+    m, fm, o, R, h0, u0 = igw
+    say("scheme", scheme, M, n)
+    rng = np.random.default_rng(11)
+    h = h0 + 0.2 * rng.standard_normal(m.nCells)
+    c = make_ctx(m, fm)
+    c.init_state(h, u0)
+    c.step_scheme(scheme, 30.0, M, n)
+    gh, gu = c.get_state()
+    if scheme == "lts2":
+        rh, ru = o.lts(h, u0, 30.0, M, R, n=n, order=2)
+    elif scheme == "lts3":
+        rh, ru = o.lts(h, u0, 30.0, M, R, n=n, order=3)
+    elif scheme == "ssprk2":
+        rh, ru = o.ssprk(h, u0, 30.0, n=n, order=2)
+    else:
+        rh, ru = o.rk4(h, u0, 30.0, n=n)
+    assert rel_l2(gh, rh, m.areaCell) < 1e-12
+    assert rel_l2(gu, ru) < 1e-11
+    if scheme in ("lts2", "lts3"):
+        d0m, _ = o.diagnostics(h, u0)
+        assert abs(c.diagnostics().mass - d0m) / d0m < 1e-13
+    c.close()

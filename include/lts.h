@@ -187,6 +187,45 @@ lts_status lts_plan(const lts_mesh *mesh, const uint8_t *fine_mask, int n_if1_ri
 const char *lts_last_error(const lts_ctx *ctx);
 void lts_destroy(lts_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+   Ensembles: many independent LTS3 runs of uneven size advanced together.
+   Each member has its own mesh, regions, coarse step dt and ratio M; one
+   ensemble step advances every member by one coarse step.  The members'
+   passes are batched into shared launches over device work lists (one per
+   phase, kernel class and member size class: < 30k cells, < 120k, larger),
+   the size classes run as concurrent branches of one hipGraph, and an
+   autotuner picks block and grid size per (kernel class, size class).
+   Results equal lts_step on each member alone (same kernels and arithmetic).
+   Call order: create, add_member..., init_member (every member), build,
+   step..., get_member / diagnostics, destroy.  Not thread-safe. */
+typedef struct lts_ens lts_ens;
+
+lts_status lts_ens_create(lts_ens **out, int device, lts_precision prec, void *hip_stream);
+/* Add a member (arguments as lts_upload_mesh, plus its coarse step and M);
+   *member receives its index.  LTS_ESTATE after lts_ens_build. */
+lts_status lts_ens_add_member(lts_ens *ens, const lts_mesh *mesh, const uint8_t *fine_mask,
+                              int n_if1_rings, int n_if2_rings, double gravity, double dt_coarse,
+                              int M, int *member);
+/* Host state of one member (caller numbering), as lts_init_state. */
+lts_status lts_ens_init_member(lts_ens *ens, int member, const double *h, const double *u);
+/* Plan the work lists, autotune when autotune != 0 (member states are
+   restored afterwards), capture the step graph.  Every member must be
+   initialised. */
+lts_status lts_ens_build(lts_ens *ens, int autotune);
+/* Advance every member by n_steps coarse steps.  Asynchronous. */
+lts_status lts_ens_step(lts_ens *ens, int n_steps);
+lts_status lts_ens_get_member(lts_ens *ens, int member, double *h, double *u);
+lts_status lts_ens_diagnostics(lts_ens *ens, int member, lts_diag *out);
+/* Autotuner choices: tuned[(k*3+s)*2 + {0,1}] = block size, grid factor (grid =
+   factor x compute units) for kernel class k (0 vertex, 1 cell, 2 edge) and
+   size class s; tuned_us[k*3+s] = the timed microseconds of that choice;
+   class_cells[s] = cells per size class; *n_launches = launches per step.
+   Any pointer may be NULL. */
+lts_status lts_ens_info(lts_ens *ens, int32_t *tuned, double *tuned_us, int64_t *class_cells,
+                        int32_t *n_launches);
+const char *lts_ens_last_error(const lts_ens *ens);
+void lts_ens_destroy(lts_ens *ens);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,8 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblts.so")
-SOURCES = [os.path.join(CSRC, "lts_api.cpp"), os.path.join(CSRC, "lts_kernels.hip")]
-HEADERS = [os.path.join(CSRC, "lts_internal.h"), os.path.join(ROOT, "include", "lts.h")]
+SOURCES = [os.path.join(CSRC, "lts_api.cpp"), os.path.join(CSRC, "lts_ensemble.cpp"),
+           os.path.join(CSRC, "lts_kernels.hip")]
+HEADERS = [os.path.join(CSRC, "lts_internal.h"), os.path.join(CSRC, "lts_host.h"),
+           os.path.join(ROOT, "include", "lts.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP translation unit.

@@ -1,0 +1,433 @@
+// Ensemble runtime of liblts: many independent LTS3 runs (members) of uneven
+// size advanced together.
+//
+// Each member is an ordinary context (its own mesh, regions, coefficients and
+// state).  A member's coarse step is the sequence of right-hand-side passes of
+// Algorithm 2.2 (3 M + 4 passes, each a vertex, a cell and an edge kernel).
+// The ensemble runs phase t of every member that has one in shared launches:
+// one launch per (phase, kernel class, size class) over a device work list of
+// (member, range, epilogue) items, with a persistent grid that strides over the
+// list's virtual blocks.  Members fall in three size classes (< 30k cells,
+// < 120k, larger); each class is an independent chain of launches on its own
+// stream, and the whole ensemble step is captured once into a hipGraph whose
+// three branches run concurrently.  An autotuner times block size and grid
+// size for every (kernel class, size class) on the members' own data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lts_host.h"
+
+using namespace lts;
+
+struct lts_ens {
+    int device = 0;
+    lts_precision prec = LTS_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+    std::vector<lts_ctx*> members;
+    std::vector<double> dt;
+    std::vector<int> M, sclass;
+    bool built = false;
+    int G = 0;
+    int n_cu = 256;
+    // tuned launch shape per [kernel class][size class]: block size, grid factor
+    int tune_block[KC_N][3] = {{256, 256, 256}, {256, 256, 256}, {256, 256, 256}};
+    int tune_pf[KC_N][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
+    double tune_us[KC_N][3] = {{0}};
+    struct Launch {
+        int sc, kclass, nitems, nvb, block, grid;
+        size_t off;  // first item in d_items
+    };
+    std::vector<Launch> launches;
+    void* d_items = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t steps = 0;
+};
+
+namespace {
+
+lts_status efail(lts_ens* e, lts_status s, const std::string& msg) {
+    if (e) e->err = msg;
+    return s;
+}
+
+#define EHIP(e, expr)                                                                        \
+    do {                                                                                     \
+        hipError_t r_ = (expr);                                                              \
+        if (r_ != hipSuccess)                                                                \
+            return efail(e, LTS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(r_)); \
+    } while (0)
+
+int size_class(int n_cells) { return n_cells < 30000 ? 0 : n_cells < 120000 ? 1 : 2; }
+
+template <typename T>
+struct Builder {
+    lts_ens* e;
+    std::vector<std::vector<PassRecord<T>>> recs;  // per member, in step order
+    int nphase = 0;
+
+    lts_status record() {
+        recs.assign(e->members.size(), {});
+        nphase = 0;
+        for (size_t j = 0; j < e->members.size(); ++j) {
+            lts_ctx* c = e->members[j];
+            const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+            Run<T> r{c, dm, e->stream, false};
+            r.rec = &recs[j];
+            lts_status st = r.lts3_step(e->dt[j], e->M[j]);
+            if (st) return efail(e, st, "recording member " + std::to_string(j) + ": " + c->err);
+            nphase = std::max(nphase, (int)recs[j].size());
+        }
+        return LTS_OK;
+    }
+
+    // Work items of one launch; returns the number of virtual blocks.
+    int items(int t, int sc, int kclass, int block, std::vector<Item<T>>& out) const {
+        out.clear();
+        int first = 0;
+        for (size_t j = 0; j < recs.size(); ++j) {
+            if (e->sclass[j] != sc || t >= (int)recs[j].size()) continue;
+            lts_ctx* c = e->members[j];
+            const PassRecord<T>& r = recs[j][t];
+            const PassPlan& P = c->plan[r.kind];
+            Item<T> w;
+            w.m = *static_cast<DevMesh<T>*>(c->dm);
+            w.h = r.h;
+            w.u = r.u;
+            w.q = static_cast<T*>(c->q);
+            w.zs = static_cast<T*>(c->zs);
+            w.flag = c->flag;
+            w.g = (T)c->g;
+            long n = 0;
+            if (kclass == KC_VERTEX) {
+                w.lo = P.v_lo;
+                w.hi = P.v_hi;
+                n = P.v_hi - P.v_lo;
+            } else if (kclass == KC_CELL) {
+                w.lo = P.c_lo;
+                w.hi = P.c_hi;
+                w.s0 = r.cs0;
+                w.s1 = r.cs1;
+                n = (long)(P.c_hi - P.c_lo) * e->G;
+            } else {
+                w.lo = P.et_lo;
+                w.hi = P.et_hi;
+                w.s0 = r.es0;
+                w.s1 = r.es1;
+                w.aux = r.aux;
+                n = P.et_hi - P.et_lo;
+                if (r.aux.kind) w.nblk_aux = (int)((r.aux.nh + r.aux.nu + block - 1) / block);
+            }
+            w.nblk = (int)((n + block - 1) / block);
+            if (w.nblk + w.nblk_aux == 0) continue;
+            w.first = first;
+            first += w.nblk + w.nblk_aux;
+            out.push_back(w);
+        }
+        return first;
+    }
+
+    // Time candidate (block, grid factor) pairs for every (kernel class, size
+    // class) on the phase with the most work for it.
+    lts_status autotune() {
+        const int blocks[3] = {128, 256, 512};
+        const int pfs[4] = {1, 2, 4, 8};
+        std::vector<Item<T>> it;
+        void* dbuf = nullptr;
+        size_t dcap = 0;
+        hipEvent_t a, b;
+        EHIP(e, hipEventCreate(&a));
+        EHIP(e, hipEventCreate(&b));
+        for (int k = 0; k < KC_N; ++k)
+            for (int sc = 0; sc < 3; ++sc) {
+                int best_t = -1, best_n = 0;
+                for (int t = 0; t < nphase; ++t) {
+                    const int n = items(t, sc, k, 256, it);
+                    if (n > best_n) { best_n = n; best_t = t; }
+                }
+                if (best_t < 0) continue;
+                double best = 1e30;
+                for (int bs : blocks) {
+                    const int nvb = items(best_t, sc, k, bs, it);
+                    const size_t bytes = it.size() * sizeof(Item<T>);
+                    if (bytes > dcap) {
+                        if (dbuf) (void)hipFree(dbuf);
+                        EHIP(e, hipMalloc(&dbuf, bytes));
+                        dcap = bytes;
+                    }
+                    EHIP(e, hipMemcpy(dbuf, it.data(), bytes, hipMemcpyHostToDevice));
+                    for (int pf : pfs) {
+                        const int grid = std::max(1, std::min(nvb, pf * e->n_cu));
+                        const Item<T>* di = static_cast<const Item<T>*>(dbuf);
+                        for (int w = 0; w < 2; ++w)
+                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, e->G, e->stream));
+                        EHIP(e, hipEventRecord(a, e->stream));
+                        const int reps = 8;
+                        for (int w = 0; w < reps; ++w)
+                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, e->G, e->stream));
+                        EHIP(e, hipEventRecord(b, e->stream));
+                        EHIP(e, hipEventSynchronize(b));
+                        float ms = 0;
+                        EHIP(e, hipEventElapsedTime(&ms, a, b));
+                        const double us = 1e3 * ms / reps;
+                        if (us < best) {
+                            best = us;
+                            e->tune_block[k][sc] = bs;
+                            e->tune_pf[k][sc] = pf;
+                            e->tune_us[k][sc] = us;
+                        }
+                    }
+                }
+            }
+        if (dbuf) (void)hipFree(dbuf);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return LTS_OK;
+    }
+
+    lts_status finalize() {
+        std::vector<Item<T>> all, it;
+        e->launches.clear();
+        for (int sc = 0; sc < 3; ++sc)
+            for (int t = 0; t < nphase; ++t)
+                for (int k = 0; k < KC_N; ++k) {
+                    const int bs = e->tune_block[k][sc];
+                    const int nvb = items(t, sc, k, bs, it);
+                    if (nvb == 0) continue;
+                    lts_ens::Launch L;
+                    L.sc = sc;
+                    L.kclass = k;
+                    L.nitems = (int)it.size();
+                    L.nvb = nvb;
+                    L.block = bs;
+                    L.grid = std::max(1, std::min(nvb, e->tune_pf[k][sc] * e->n_cu));
+                    L.off = all.size();
+                    all.insert(all.end(), it.begin(), it.end());
+                    e->launches.push_back(L);
+                }
+        const size_t bytes = std::max<size_t>(all.size(), 1) * sizeof(Item<T>);
+        EHIP(e, hipMalloc(&e->d_items, bytes));
+        if (!all.empty())
+            EHIP(e, hipMemcpy(e->d_items, all.data(), all.size() * sizeof(Item<T>),
+                              hipMemcpyHostToDevice));
+        // capture: fork to one stream per size class, one chain each, join
+        EHIP(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipEventRecord(e->fork, e->stream);
+        for (int sc = 0; sc < 3 && err == hipSuccess; ++sc)
+            err = hipStreamWaitEvent(e->side[sc], e->fork, 0);
+        const Item<T>* base = static_cast<const Item<T>*>(e->d_items);
+        for (const auto& L : e->launches) {
+            if (err != hipSuccess) break;
+            err = launch_batch<T>(L.kclass, base + L.off, L.nitems, L.nvb, L.block, L.grid, e->G,
+                                  e->side[L.sc]);
+        }
+        for (int sc = 0; sc < 3 && err == hipSuccess; ++sc) {
+            err = hipEventRecord(e->join[sc], e->side[sc]);
+            if (err == hipSuccess) err = hipStreamWaitEvent(e->stream, e->join[sc], 0);
+        }
+        hipGraph_t gr = nullptr;
+        hipError_t err2 = hipStreamEndCapture(e->stream, &gr);
+        if (err != hipSuccess || err2 != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return efail(e, LTS_EDEVICE, std::string("ensemble capture: ") +
+                                             hipGetErrorString(err != hipSuccess ? err : err2));
+        }
+        e->graph = gr;
+        EHIP(e, hipGraphInstantiate(&e->gexec, gr, nullptr, nullptr, 0));
+        return LTS_OK;
+    }
+};
+
+template <typename T>
+lts_status build(lts_ens* e, int autotune) {
+    Builder<T> b{e};
+    lts_status st = b.record();
+    if (st) return st;
+    if (autotune) {
+        // tuning launches advance the members: keep their states and restore them
+        std::vector<std::vector<double>> h(e->members.size()), u(e->members.size());
+        for (size_t j = 0; j < e->members.size(); ++j) {
+            h[j].resize(e->members[j]->nC);
+            u[j].resize(e->members[j]->nE);
+            if ((st = lts_get_state(e->members[j], h[j].data(), u[j].data())))
+                return efail(e, st, e->members[j]->err);
+        }
+        if ((st = b.autotune())) return st;
+        EHIP(e, hipStreamSynchronize(e->stream));
+        for (size_t j = 0; j < e->members.size(); ++j) {
+            lts_ctx* c = e->members[j];
+            const double t0 = c->t;
+            if ((st = lts_init_state(c, h[j].data(), u[j].data(), t0))) return efail(e, st, c->err);
+        }
+    }
+    return b.finalize();
+}
+
+lts_status ens_ready(lts_ens* e) {
+    if (!e) return LTS_EINVAL;
+    if (hipSetDevice(e->device) != hipSuccess) return efail(e, LTS_EDEVICE, "hipSetDevice");
+    return LTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_ens_create(lts_ens** out, int device, lts_precision prec, void* hip_stream) {
+    if (!out) return LTS_EINVAL;
+    *out = nullptr;
+    if (prec != LTS_FP64 && prec != LTS_FP32) return LTS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LTS_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LTS_EDEVICE;
+    lts_ens* e = new lts_ens();
+    e->device = device;
+    e->prec = prec;
+    bool ok = true;
+    if (hip_stream) {
+        e->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
+        e->own_stream = ok;
+    }
+    for (int k = 0; k < 3 && ok; ++k)
+        ok = hipStreamCreateWithFlags(&e->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&e->join[k], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) == hipSuccess;
+    hipDeviceProp_t prop;
+    if (ok && hipGetDeviceProperties(&prop, device) == hipSuccess) e->n_cu = prop.multiProcessorCount;
+    *out = e;
+    return ok ? LTS_OK : efail(e, LTS_EDEVICE, "stream/event creation failed");
+}
+
+void lts_ens_destroy(lts_ens* e) {
+    if (!e) return;
+    (void)hipSetDevice(e->device);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->d_items) (void)hipFree(e->d_items);
+    for (lts_ctx* c : e->members) lts_destroy(c);
+    for (int k = 0; k < 3; ++k) {
+        if (e->side[k]) (void)hipStreamDestroy(e->side[k]);
+        if (e->join[k]) (void)hipEventDestroy(e->join[k]);
+    }
+    if (e->fork) (void)hipEventDestroy(e->fork);
+    if (e->own_stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+const char* lts_ens_last_error(const lts_ens* e) { return e ? e->err.c_str() : "null ensemble"; }
+
+lts_status lts_ens_add_member(lts_ens* e, const lts_mesh* mesh, const uint8_t* fine_mask,
+                              int n_if1_rings, int n_if2_rings, double gravity, double dt_coarse,
+                              int M, int* member) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (e->built) return efail(e, LTS_ESTATE, "ensemble already built");
+    if (!mesh || !(dt_coarse > 0) || M < 1) return efail(e, LTS_EINVAL, "bad member arguments");
+    lts_ctx* c = nullptr;
+    if ((s = lts_create(&c, e->device, e->prec, e->stream))) return efail(e, s, "member context");
+    if ((s = lts_upload_mesh(c, mesh, fine_mask, n_if1_rings, n_if2_rings, gravity))) {
+        const std::string msg = c->err;
+        lts_destroy(c);
+        return efail(e, s, "member mesh: " + msg);
+    }
+    const int G = padded_slots(c->maxE);
+    if (e->G && G != e->G) {
+        lts_destroy(c);
+        return efail(e, LTS_EMESH, "members must share the slot count (max_edges <= 8 or > 8)");
+    }
+    e->G = G;
+    e->members.push_back(c);
+    e->dt.push_back(dt_coarse);
+    e->M.push_back(M);
+    e->sclass.push_back(size_class(c->nC));
+    if (member) *member = (int)e->members.size() - 1;
+    return LTS_OK;
+}
+
+lts_status lts_ens_init_member(lts_ens* e, int member, const double* h, const double* u) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (member < 0 || member >= (int)e->members.size()) return efail(e, LTS_EINVAL, "no such member");
+    if ((s = lts_init_state(e->members[member], h, u, 0.0)))
+        return efail(e, s, e->members[member]->err);
+    return LTS_OK;
+}
+
+lts_status lts_ens_build(lts_ens* e, int autotune) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (e->built) return efail(e, LTS_ESTATE, "ensemble already built");
+    if (e->members.empty()) return efail(e, LTS_ESTATE, "no members");
+    for (lts_ctx* c : e->members)
+        if (!c->has_state) return efail(e, LTS_ESTATE, "initialise every member before build");
+    s = e->prec == LTS_FP64 ? build<double>(e, autotune) : build<float>(e, autotune);
+    if (s) return s;
+    e->built = true;
+    return LTS_OK;
+}
+
+lts_status lts_ens_step(lts_ens* e, int n_steps) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (!e->built) return efail(e, LTS_ESTATE, "build the ensemble first");
+    if (n_steps < 0) return efail(e, LTS_EINVAL, "n_steps < 0");
+    for (lts_ctx* c : e->members)
+        if (c->nonfinite) return efail(e, LTS_ENONFINITE, "a member is non-finite");
+    for (int i = 0; i < n_steps; ++i) EHIP(e, hipGraphLaunch(e->gexec, e->stream));
+    for (size_t j = 0; j < e->members.size(); ++j) {
+        e->members[j]->t += e->dt[j] * n_steps;
+        e->members[j]->steps += n_steps;
+    }
+    e->steps += n_steps;
+    return LTS_OK;
+}
+
+lts_status lts_ens_get_member(lts_ens* e, int member, double* h, double* u) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (member < 0 || member >= (int)e->members.size()) return efail(e, LTS_EINVAL, "no such member");
+    if ((s = lts_get_state(e->members[member], h, u))) return efail(e, s, e->members[member]->err);
+    return LTS_OK;
+}
+
+lts_status lts_ens_diagnostics(lts_ens* e, int member, lts_diag* out) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (member < 0 || member >= (int)e->members.size()) return efail(e, LTS_EINVAL, "no such member");
+    s = lts_diagnostics(e->members[member], out);
+    if (s) return efail(e, s, e->members[member]->err);
+    return LTS_OK;
+}
+
+lts_status lts_ens_info(lts_ens* e, int32_t* tuned, double* tuned_us, int64_t* class_cells,
+                        int32_t* n_launches) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    for (int k = 0; k < KC_N; ++k)
+        for (int sc = 0; sc < 3; ++sc) {
+            if (tuned) {
+                tuned[(k * 3 + sc) * 2] = e->tune_block[k][sc];
+                tuned[(k * 3 + sc) * 2 + 1] = e->tune_pf[k][sc];
+            }
+            if (tuned_us) tuned_us[k * 3 + sc] = e->tune_us[k][sc];
+        }
+    if (class_cells) {
+        for (int sc = 0; sc < 3; ++sc) class_cells[sc] = 0;
+        for (size_t j = 0; j < e->members.size(); ++j) class_cells[e->sclass[j]] += e->members[j]->nC;
+    }
+    if (n_launches) *n_launches = (int32_t)e->launches.size();
+    return LTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,451 @@
+// Host-side internals of liblts shared by the single-mesh runtime
+// (lts_api.cpp) and the ensemble runtime (lts_ensemble.cpp).  Not public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lts_internal.h"
+
+namespace lts {
+
+enum PassKind { P_FULL = 0, P_STEP1, P_STEP2, P_STEP3, P_STEP4, P_N };
+
+struct PassPlan {
+    int c_lo = 0, c_hi = 0;    // cell kernel range (targets plus cells of target edges)
+    int v_lo = 0, v_hi = 0;    // vertex kernel range
+    int ct_lo = 0, ct_hi = 0;  // target cells
+    int et_lo = 0, et_hi = 0;  // target edges
+    // algorithmic bytes of the gathers, per element type (counts of unique
+    // elements touched), filled at upload
+    long v_uniq_u = 0, v_uniq_h = 0;
+    long c_uniq_h = 0, c_uniq_u = 0, c_uniq_q = 0, c_slots = 0;
+};
+
+struct TimedLaunch {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+}  // namespace lts
+
+struct lts_ctx {
+    int device = 0;
+    lts_precision prec = LTS_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    bool has_mesh = false, has_state = false, nonfinite = false;
+    int nC = 0, nE = 0, nV = 0, maxE = 0;
+    double g = 9.81;
+    std::vector<int32_t> cperm, cinv, eperm, einv, vperm, vinv;  // perm: new->old, inv: old->new
+    std::vector<int8_t> creg, ereg;                              // caller numbering
+    std::vector<uint8_t> cfbar, efbar;
+    int cb[8] = {0};  // cell class starts: Fint F2 F1 I1 I2 C1 Crest end
+    int eb[6] = {0};  // edge class starts: Fint Fbar I1 I2 C end
+    lts::PassPlan plan[lts::P_N];
+
+    // device memory (typed by prec); all owned
+    std::vector<void*> allocs;
+    void* dm = nullptr;  // DevMesh<T>*
+    void *Ah = nullptr, *Au = nullptr, *Bh = nullptr, *Bu = nullptr, *Ch = nullptr, *Cu = nullptr;
+    void *x0h = nullptr, *x1h = nullptr, *x2h = nullptr, *x0u = nullptr, *x1u = nullptr,
+         *x2u = nullptr;
+    void *acch = nullptr, *accu = nullptr, *zs = nullptr, *q = nullptr;
+    void *Qh = nullptr, *Qu = nullptr;  // RK4 stage sums (allocated on first use)
+    int* flag = nullptr;
+    double *dpart = nullptr, *dout = nullptr;
+
+    double t = 0.0;
+    int64_t steps = 0;
+
+    // perturbation thickness form (FP32): state holds eta = h - href
+    bool pert = false;
+    std::vector<double> href_host;           // device order, value of the stored href
+    std::vector<double> bot_perm, area_perm; // device order
+    void *d_href = nullptr, *d_beta = nullptr;
+
+    // graph cache for one step of one scheme
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_kind = -1, g_M = 0;
+    double g_dt = 0.0;
+
+    // timing
+    bool timing = false;
+    std::vector<lts::TimedLaunch> pending;
+    std::vector<hipEvent_t> evpool;
+    int64_t st_launch[lts::KC_N] = {0};
+    double st_ms[lts::KC_N] = {0}, st_bytes[lts::KC_N] = {0};
+};
+
+namespace lts {
+
+lts_status fail(lts_ctx* c, lts_status s, const std::string& msg);
+size_t tsize(const lts_ctx* c);
+lts_status dalloc(lts_ctx* c, void** p, size_t bytes);
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::lts::fail(ctx, LTS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// One right-hand-side pass as recorded instead of launched (the ensemble
+// batches the passes of many members into shared launches).
+template <typename T>
+struct PassRecord {
+    int kind;
+    const T* h;
+    const T* u;
+    Seg<T> cs0, cs1, es0, es1;
+    Aux<T> aux;
+};
+
+// ---------------------------------------------------------------- launches
+// Enqueues the passes of one step of a scheme for one context: launches them
+// on stream s (event-stamped when timed), or, when rec is set, records them so
+// the ensemble can batch them with other members' passes.
+template <typename T>
+struct Run {
+    lts_ctx* c;
+    const DevMesh<T>& dm;
+    hipStream_t s;
+    bool timed;
+    std::vector<PassRecord<T>>* rec = nullptr;
+
+    // Two events for an event-stamped launch (timing mode only).
+    lts_status events(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
+        if (!timed) return LTS_OK;
+        while (c->evpool.size() < 2) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->evpool.push_back(e);
+        }
+        *a = c->evpool.back();
+        c->evpool.pop_back();
+        *b = c->evpool.back();
+        c->evpool.pop_back();
+        return LTS_OK;
+    }
+    void done(int cls, hipEvent_t a, hipEvent_t b, double bytes) {
+        if (timed) c->pending.push_back({cls, a, b, bytes});
+    }
+
+    static double seg_bytes(const Seg<T>& g) {
+        if (!g.mode || g.hi <= g.lo) return 0.0;
+        const double n = g.hi - g.lo;
+        if (g.mode == 1) return n * sizeof(T) * (1 + (g.xold ? 1 : 0) + (g.xcur ? 1 : 0));
+        return n * sizeof(T) * (g.first ? 1 : 2);
+    }
+
+    // One right-hand-side pass of kind p over state (h, u) with epilogues.
+    lts_status pass(int p, const T* h, const T* u, const Seg<T>& cs0, const Seg<T>& cs1,
+                    const Seg<T>& es0, const Seg<T>& es1, const Aux<T>& aux = Aux<T>()) {
+        if (rec) {
+            rec->push_back(PassRecord<T>{p, h, u, cs0, cs1, es0, es1, aux});
+            return LTS_OK;
+        }
+        const PassPlan& P = c->plan[p];
+        T* q = static_cast<T*>(c->q);
+        T* zs = static_cast<T*>(c->zs);
+        const double ts = sizeof(T);
+        hipEvent_t e0, e1;
+        lts_status st;
+        // vertex PV
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
+        const double nv = P.v_hi - P.v_lo;
+        done(KC_VERTEX, e0, e1, nv * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts);
+        // cell tendency + partials
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag, s,
+                                 e0, e1));
+        const double ncell = P.c_hi - P.c_lo;
+        const double cb = ncell * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
+                          (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(cs0) +
+                          seg_bytes(cs1);
+        done(KC_CELL, e0, e1, cb);
+        // edge tendency (+ appended element-wise job)
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1));
+        const double eb = (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(es0) + seg_bytes(es1) +
+                          (aux.kind == 1 ? 4.0 : aux.kind == 2 ? 3.0 : 0.0) * (aux.nh + aux.nu) * ts;
+        done(KC_EDGE, e0, e1, eb);
+        return LTS_OK;
+    }
+
+    static Seg<T> upd(int lo, int hi, T* out, const T* xold, double a_old, const T* xcur,
+                      double a_cur, double a_dt) {
+        Seg<T> g;
+        g.lo = lo;
+        g.hi = hi;
+        g.mode = hi > lo ? 1 : 0;
+        g.out = out;
+        g.xold = xold;
+        g.a_old = (T)a_old;
+        g.xcur = xcur;
+        g.a_cur = (T)a_cur;
+        g.a_dt = (T)a_dt;
+        return g;
+    }
+    static Seg<T> mirror(Seg<T> g, int mlo, int mhi, T* mnew, T* mcur) {
+        g.mlo = mlo;
+        g.mhi = mhi;
+        g.mnew = mnew;
+        g.mcur = mcur;
+        return g;
+    }
+    Aux<T> predict_aux(T* xh, T* xu, int stage, int k, int M, int order = 3) {
+        Aux<T> x;
+        double cf[3];
+        predict_coeffs(stage, k, M, cf, order);
+        x.kind = 1;
+        x.nh = c->cb[4] - c->cb[3];
+        x.nu = c->eb[3] - c->eb[2];
+        x.lo_h = c->cb[3];
+        x.lo_u = c->eb[2];
+        x.xh = xh;
+        x.xu = xu;
+        x.ah = (T*)c->x0h; x.bh = (T*)c->x1h; x.ch = (T*)c->x2h;
+        x.au = (T*)c->x0u; x.bu = (T*)c->x1u; x.cu = (T*)c->x2u;
+        x.c0 = cf[0]; x.c1 = cf[1]; x.c2 = cf[2];
+        return x;
+    }
+    Aux<T> correct_aux(double delta) {
+        Aux<T> x;
+        x.kind = 2;
+        x.nh = c->cb[5] - c->cb[3];
+        x.nu = c->eb[4] - c->eb[2];
+        x.nbh = c->cb[4] - c->cb[3];
+        x.nbu = c->eb[3] - c->eb[2];
+        x.lo_h = c->cb[3];
+        x.lo_u = c->eb[2];
+        x.xh = (T*)c->Ah;
+        x.xu = (T*)c->Au;
+        x.ah = (T*)c->x0h; x.bh = (T*)c->acch;
+        x.au = (T*)c->x0u; x.bu = (T*)c->accu;
+        x.c0 = delta;
+        return x;
+    }
+    static Seg<T> accum(int lo, int hi, T* acc, double theta, bool first) {
+        Seg<T> g;
+        g.lo = lo;
+        g.hi = hi;
+        g.mode = hi > lo ? 2 : 0;
+        g.acc = acc;
+        g.theta = (T)theta;
+        g.first = first ? 1 : 0;
+        return g;
+    }
+
+    // Algorithm 2.2, order 3: one coarse step on the state in A.  The
+    // interface-1 copies of X0, X1, X2 are written by the stage epilogues; each
+    // interface-1 prediction and the final interface correction run as extra
+    // blocks of the preceding edge kernel (they touch none of its data).
+    lts_status lts3_step(double dt, int M) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu;
+        const int* cb = c->cb;
+        const int* eb = c->eb;
+        const int nC = c->nC, nE = c->nE;
+        const double delta = dt / M;
+        const Seg<T> none;
+        lts_status st;
+        // Step 1: first stage with dt on underlined F, I1, I2, C
+        if ((st = pass(P_STEP1, Ah, Au,
+                       mirror(upd(cb[1], nC, Bh, nullptr, 0, Ah, 1, dt), cb[3], cb[4],
+                              (T*)c->x1h, (T*)c->x0h),
+                       none,
+                       mirror(upd(eb[1], nE, Bu, nullptr, 0, Au, 1, dt), eb[2], eb[3],
+                              (T*)c->x1u, (T*)c->x0u),
+                       none)))
+            return st;
+        // Step 2: second stage with dt on I1, I2, C
+        if ((st = pass(P_STEP2, Bh, Bu,
+                       mirror(upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), cb[3], cb[4],
+                              (T*)c->x2h, nullptr),
+                       none,
+                       mirror(upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), eb[2], eb[3],
+                              (T*)c->x2u, nullptr),
+                       none)))
+            return st;
+        // Step 3: M fine SSPRK3 substeps on F; I1 predicted, I accumulates.
+        // (Stage (old,0) needs no prediction: its coefficients give X0.)
+        for (int k = 0; k < M; ++k) {
+            // stage (old,k): A holds F at substep k, X0 on I2 and C
+            if ((st = pass(P_STEP3, Ah, Au, upd(0, cb[3], Bh, nullptr, 0, Ah, 1, delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, k == 0),
+                           upd(0, eb[2], Bu, nullptr, 0, Au, 1, delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, k == 0),
+                           predict_aux(Bh, Bu, 1, k, M))))
+                return st;
+            // stage (1st,k): B holds stage-1 F, X1 on I2 and C
+            if ((st = pass(P_STEP3, Bh, Bu, upd(0, cb[3], Ch, Ah, 0.75, Bh, 0.25, 0.25 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 1.0 / 6.0, false),
+                           upd(0, eb[2], Cu, Au, 0.75, Bu, 0.25, 0.25 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 1.0 / 6.0, false),
+                           predict_aux(Ch, Cu, 2, k, M))))
+                return st;
+            // stage (2nd,k): C holds stage-2 F, X2 on I2 and C; new F into A
+            if ((st = pass(P_STEP3, Ch, Cu,
+                           upd(0, cb[3], Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 2.0 / 3.0, false),
+                           upd(0, eb[2], Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 2.0 / 3.0, false),
+                           k + 1 < M ? predict_aux(Ah, Au, 0, k + 1, M) : Aux<T>())))
+                return st;
+        }
+        // Step 4: third stage with dt on C (reads X2 in C and I2 only); Step 5,
+        // the interface correction x = x_old + dt/M * acc on I1 u I2, rides on
+        // its edge kernel.
+        return pass(P_STEP4, Ch, Cu,
+                    upd(cb[5], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
+                    upd(eb[4], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
+                    correct_aux(delta));
+    }
+
+    // Algorithm 2.1, SSPRK3, over the whole mesh.
+    lts_status rk3_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        if ((st = pass(P_FULL, Ah, Au, upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), none,
+                       upd(0, nE, Bu, nullptr, 0, Au, 1, dt), none)))
+            return st;
+        if ((st = pass(P_FULL, Bh, Bu, upd(0, nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), none,
+                       upd(0, nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), none)))
+            return st;
+        return pass(P_FULL, Ch, Cu, upd(0, nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                    none, upd(0, nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt), none);
+    }
+
+    // Algorithm 2.1, SSPRK2, over the whole mesh.
+    lts_status ssprk2_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        if ((st = pass(P_FULL, Ah, Au, upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), none,
+                       upd(0, nE, Bu, nullptr, 0, Au, 1, dt), none)))
+            return st;
+        return pass(P_FULL, Bh, Bu, upd(0, nC, Ah, Ah, 0.5, Bh, 0.5, 0.5 * dt), none,
+                    upd(0, nE, Au, Au, 0.5, Bu, 0.5, 0.5 * dt), none);
+    }
+
+    // Classical RK4 over the whole mesh: the stage sum k1 + 2 k2 + 2 k3 is
+    // accumulated in Q by the stage epilogues, the last stage adds dt/6 (Q + k4).
+    lts_status rk4_step(double dt) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu, *Qh = (T*)c->Qh, *Qu = (T*)c->Qu;
+        const int nC = c->nC, nE = c->nE;
+        const Seg<T> none;
+        lts_status st;
+        auto with_acc = [](Seg<T> g, T* acc, double theta, bool first) {
+            g.acc = acc;
+            g.theta = (T)theta;
+            g.first = first ? 1 : 0;
+            return g;
+        };
+        if ((st = pass(P_FULL, Ah, Au,
+                       with_acc(upd(0, nC, Bh, nullptr, 0, Ah, 1, 0.5 * dt), Qh, 1.0, true), none,
+                       with_acc(upd(0, nE, Bu, nullptr, 0, Au, 1, 0.5 * dt), Qu, 1.0, true), none)))
+            return st;
+        if ((st = pass(P_FULL, Bh, Bu,
+                       with_acc(upd(0, nC, Ch, nullptr, 0, Ah, 1, 0.5 * dt), Qh, 2.0, false), none,
+                       with_acc(upd(0, nE, Cu, nullptr, 0, Au, 1, 0.5 * dt), Qu, 2.0, false), none)))
+            return st;
+        if ((st = pass(P_FULL, Ch, Cu,
+                       with_acc(upd(0, nC, Bh, nullptr, 0, Ah, 1, dt), Qh, 2.0, false), none,
+                       with_acc(upd(0, nE, Bu, nullptr, 0, Au, 1, dt), Qu, 2.0, false), none)))
+            return st;
+        return pass(P_FULL, Bh, Bu, upd(0, nC, Ah, Ah, 1.0, Qh, dt / 6.0, dt / 6.0), none,
+                    upd(0, nE, Au, Au, 1.0, Qu, dt / 6.0, dt / 6.0), none);
+    }
+
+    // Algorithm 2.2, order 2 (LTS2).  Step 2 (the coarse second stage on C)
+    // reads only X0 and X1, and nothing in Step 3 reads its result, so it runs
+    // after the substeps, writing the new coarse values straight into A with
+    // the interface correction riding on its edge kernel.
+    lts_status lts2_step(double dt, int M) {
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu;
+        const int* cb = c->cb;
+        const int* eb = c->eb;
+        const int nC = c->nC, nE = c->nE;
+        const double delta = dt / M;
+        const Seg<T> none;
+        lts_status st;
+        // Step 1: first stage with dt on I1, I2, C
+        if ((st = pass(P_STEP2, Ah, Au,
+                       mirror(upd(cb[3], nC, Bh, nullptr, 0, Ah, 1, dt), cb[3], cb[4],
+                              (T*)c->x1h, (T*)c->x0h),
+                       none,
+                       mirror(upd(eb[2], nE, Bu, nullptr, 0, Au, 1, dt), eb[2], eb[3],
+                              (T*)c->x1u, (T*)c->x0u),
+                       none)))
+            return st;
+        for (int k = 0; k < M; ++k) {
+            if ((st = pass(P_STEP3, Ah, Au, upd(0, cb[3], Bh, nullptr, 0, Ah, 1, delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 0.5, k == 0),
+                           upd(0, eb[2], Bu, nullptr, 0, Au, 1, delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 0.5, k == 0),
+                           predict_aux(Bh, Bu, 1, k, M, 2))))
+                return st;
+            if ((st = pass(P_STEP3, Bh, Bu,
+                           upd(0, cb[3], Ah, Ah, 0.5, Bh, 0.5, 0.5 * delta),
+                           accum(cb[3], cb[5], (T*)c->acch, 0.5, false),
+                           upd(0, eb[2], Au, Au, 0.5, Bu, 0.5, 0.5 * delta),
+                           accum(eb[2], eb[4], (T*)c->accu, 0.5, false),
+                           k + 1 < M ? predict_aux(Ah, Au, 0, k + 1, M, 2) : Aux<T>())))
+                return st;
+        }
+        // Step 2 on C: new = 1/2 X0 + 1/2 X1 + 1/2 dt R(X1), into A; Step 5 rides along
+        return pass(P_STEP4, Bh, Bu, upd(cb[5], nC, Ah, Ah, 0.5, Bh, 0.5, 0.5 * dt), none,
+                    upd(eb[4], nE, Au, Au, 0.5, Bu, 0.5, 0.5 * dt), none, correct_aux(delta));
+    }
+
+    // Interface-1 prediction coefficients of Algorithm 2.2 (Steps 3.1.1,
+    // 3.2.1, 3.3.1), in FP64: (1 - a - a~, a - a~, 2 a~); a~ = 0 for LTS2.
+    static void predict_coeffs(int stage, int k, int M, double out[3], int order = 3) {
+        const double dk = k, dM = M;
+        double a, at;
+        if (stage == 0) {
+            a = dk / dM;
+            at = order == 3 ? (dk * dk) / (dM * dM) : 0.0;
+        } else if (stage == 1) {
+            a = (dk + 1.0) / dM;
+            at = order == 3 ? dk * (dk + 2.0) / (dM * dM) : 0.0;
+        } else {
+            a = (2.0 * dk + 1.0) / (2.0 * dM);
+            at = (2.0 * dk * dk + 2.0 * dk + 1.0) / (2.0 * dM * dM);
+        }
+        out[0] = 1.0 - a - at;
+        out[1] = a - at;
+        out[2] = 2.0 * at;
+    }
+};
+
+enum { SCH_LTS3 = 0, SCH_LTS2 = 1, SCH_SSPRK3 = 2, SCH_SSPRK2 = 3, SCH_RK4 = 4 };
+
+template <typename T>
+lts_status one_step(Run<T>& r, int scheme, double dt, int M) {
+    switch (scheme) {
+        case SCH_LTS3: return r.lts3_step(dt, M);
+        case SCH_LTS2: return r.lts2_step(dt, M);
+        case SCH_SSPRK3: return r.rk3_step(dt);
+        case SCH_SSPRK2: return r.ssprk2_step(dt);
+        default: return r.rk4_step(dt);
+    }
+}
+
+
+}  // namespace lts

@@ -78,6 +78,28 @@ struct Aux {
 
 enum KernelClass { KC_VERTEX = 0, KC_CELL = 1, KC_EDGE = 2, KC_N = 3 };
 
+// One entry of a batched (ensemble) launch: one member's range for one kernel
+// class.  Virtual blocks [first, first + nblk) cover [lo, hi) (G lanes per cell
+// for the cell class); for the edge class nblk_aux more blocks run `aux`.
+template <typename T>
+struct Item {
+    DevMesh<T> m;
+    const T* h = nullptr;
+    const T* u = nullptr;
+    T* q = nullptr;
+    T* zs = nullptr;
+    int* flag = nullptr;
+    T g = 0;
+    int lo = 0, hi = 0, nblk = 0, nblk_aux = 0, first = 0;
+    Seg<T> s0, s1;
+    Aux<T> aux;
+};
+
+template <typename T>
+hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, int block,
+                        int grid, int G, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+
 // Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch error.
 // Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch
 // error.  With non-null ev0/ev1 the launch goes through hipExtLaunchKernelGGL,

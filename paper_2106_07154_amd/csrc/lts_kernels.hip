@@ -77,11 +77,8 @@ __device__ __forceinline__ void epilogue(int j, T G, const Seg<T>& s0, const Seg
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __restrict__ h,
-                                                   const T* __restrict__ u, T* __restrict__ q,
-                                                   int v_lo, int v_hi) {
-    const int v = v_lo + xcd_block() * kBlock + threadIdx.x;
-    if (v >= v_hi) return;
+__device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __restrict__ h,
+                                            const T* __restrict__ u, T* __restrict__ q, int v) {
     const int nV = m.nV;
     T circ = 0, hv = 0;
 #pragma unroll
@@ -92,6 +89,14 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __rest
         hv += m.kite[o] * (m.href ? m.href[c] + h[c] : h[c]);
     }
     q[v] = (m.fA[v] + circ) / hv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __restrict__ h,
+                                                   const T* __restrict__ u, T* __restrict__ q,
+                                                   int v_lo, int v_hi) {
+    const int v = v_lo + xcd_block() * kBlock + threadIdx.x;
+    if (v < v_hi) vertex_body(m, h, u, q, v);
 }
 
 // Cell kernel: one lane per edge slot, G lanes per cell (G = 8 or 16), so a
@@ -123,13 +128,12 @@ __device__ __forceinline__ T gscan(T x, int lane) {  // inclusive
     return x;
 }
 
+// t: thread index within the cell range (G lanes per cell, groups aligned).
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
-                                                 const T* __restrict__ u,
-                                                 const T* __restrict__ q, T* __restrict__ zs,
-                                                 int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
-                                                 int* flag) {
-    const int t = xcd_block() * kBlock + threadIdx.x;
+__device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restrict__ h,
+                                          const T* __restrict__ u, const T* __restrict__ q,
+                                          T* __restrict__ zs, int t, int c_lo, int c_hi, T g,
+                                          const Seg<T>& s0, const Seg<T>& s1, int* flag) {
     const int lane = t & (G - 1);
     const int ic = c_lo + t / G;
     const bool live = ic < c_hi;
@@ -163,6 +167,16 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restri
     if (live && lane == 0) epilogue(i, -t1 / m.area[i], s0, s1, flag);
 }
 
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
+                                                 const T* __restrict__ u,
+                                                 const T* __restrict__ q, T* __restrict__ zs,
+                                                 int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
+                                                 int* flag) {
+    cell_body<T, G>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g, s0, s1,
+                    flag);
+}
+
 template <typename T>
 __device__ void run_aux(const Aux<T>& x, int j) {
     if (x.kind == 1) {
@@ -187,6 +201,12 @@ __device__ void run_aux(const Aux<T>& x, int j) {
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void edge_body(const T* __restrict__ zs, int nE, int e,
+                                          const Seg<T>& s0, const Seg<T>& s1, int* flag) {
+    epilogue(e, zs[e] + zs[(size_t)nE + e], s0, s1, flag);
+}
+
 // Edge tendency U_e = Z_{c0}(e) + Z_{c1}(e) with its epilogue; blocks past the
 // edge range run the appended element-wise job.
 template <typename T>
@@ -200,9 +220,58 @@ __global__ __launch_bounds__(kBlock) void k_edge(const T* __restrict__ zs, int n
     const int b = blockIdx.x, x = b & 7, k = b >> 3, qq = nbe >> 3, r = nbe & 7;
     const int lb = x < r ? x * (qq + 1) + k : r * (qq + 1) + (x - r) * qq + k;
     const int e = lo + lb * kBlock + threadIdx.x;
-    if (e >= hi) return;
-    const T U = zs[e] + zs[(size_t)nE + e];
-    epilogue(e, U, s0, s1, flag);
+    if (e < hi) edge_body(zs, nE, e, s0, s1, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Batched (ensemble) kernels.  A launch carries a work list: item k covers
+// virtual blocks [first_k, first_k + nblk_k + nblk_aux_k) of one member's
+// range.  The grid is persistent (fixed size, chosen by the autotuner) and
+// strides over the virtual blocks; each block finds its item by binary search.
+template <typename T>
+__device__ __forceinline__ int find_item(const Item<T>* items, int nitems, int vb) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first <= vb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void kb_vertex(const Item<T>* __restrict__ items, int nitems,
+                                                 int nvb) {
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const Item<T>& w = items[find_item(items, nitems, vb)];
+        const int v = w.lo + (vb - w.first) * (int)blockDim.x + threadIdx.x;
+        if (v < w.hi) vertex_body(w.m, w.h, w.u, w.q, v);
+    }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(512) void kb_cell(const Item<T>* __restrict__ items, int nitems,
+                                               int nvb) {
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const Item<T>& w = items[find_item(items, nitems, vb)];
+        cell_body<T, G>(w.m, w.h, w.u, w.q, w.zs, (vb - w.first) * (int)blockDim.x + threadIdx.x,
+                        w.lo, w.hi, w.g, w.s0, w.s1, w.flag);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items, int nitems,
+                                               int nvb) {
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const Item<T>& w = items[find_item(items, nitems, vb)];
+        const int k = vb - w.first;
+        if (k < w.nblk) {
+            const int e = w.lo + k * (int)blockDim.x + threadIdx.x;
+            if (e < w.hi) edge_body(w.zs, w.m.nE, e, w.s0, w.s1, w.flag);
+        } else {
+            run_aux(w.aux, (k - w.nblk) * (int)blockDim.x + threadIdx.x);
+        }
+    }
 }
 
 // Diagnostics: block partials [mass, energy, -h_min, h_max, |u|max, nonfinite]
@@ -338,6 +407,33 @@ hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, co
 }
 
 template <typename T>
+hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, int block, int grid,
+                        int G, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nvb <= 0) return hipSuccess;
+    const dim3 gr(grid), bl(block);
+    if (ev0 || ev1) {
+        if (kclass == KC_VERTEX)
+            hipExtLaunchKernelGGL(kb_vertex<T>, gr, bl, 0, s, ev0, ev1, 0, items, nitems, nvb);
+        else if (kclass == KC_CELL && G == 8)
+            hipExtLaunchKernelGGL(kb_cell<T, 8>, gr, bl, 0, s, ev0, ev1, 0, items, nitems, nvb);
+        else if (kclass == KC_CELL)
+            hipExtLaunchKernelGGL(kb_cell<T, 16>, gr, bl, 0, s, ev0, ev1, 0, items, nitems, nvb);
+        else
+            hipExtLaunchKernelGGL(kb_edge<T>, gr, bl, 0, s, ev0, ev1, 0, items, nitems, nvb);
+    } else {
+        if (kclass == KC_VERTEX)
+            hipLaunchKernelGGL(kb_vertex<T>, gr, bl, 0, s, items, nitems, nvb);
+        else if (kclass == KC_CELL && G == 8)
+            hipLaunchKernelGGL((kb_cell<T, 8>), gr, bl, 0, s, items, nitems, nvb);
+        else if (kclass == KC_CELL)
+            hipLaunchKernelGGL((kb_cell<T, 16>), gr, bl, 0, s, items, nitems, nvb);
+        else
+            hipLaunchKernelGGL(kb_edge<T>, gr, bl, 0, s, items, nitems, nvb);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_diag(const DevMesh<T>& m, const T* h, const T* u, double g, double* part,
                        int nblk_cells, int nblk_edges, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_diag_part<T>, dim3(nblk_cells + nblk_edges), dim3(kBlock), 0, s, m, h,
@@ -362,6 +458,8 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
                                        hipEvent_t, hipEvent_t);                                 \
     template hipError_t launch_edge<T>(const T*, int, int, int, const Seg<T>&, const Seg<T>&,    \
                                        const Aux<T>&, int*, hipStream_t, hipEvent_t, hipEvent_t);\
+    template hipError_t launch_batch<T>(int, const Item<T>*, int, int, int, int, int,           \
+                                        hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_diag<T>(const DevMesh<T>&, const T*, const T*, double, double*,   \
                                        int, int, double*, hipStream_t);
 

@@ -90,3 +90,59 @@ def vr_planar(n=VR_N, seed=VR_SEED, iters=VR_ITERS, H=500.0, amp=5.0, sigma=4.0e
     return Workload(f"vr-planar-{n // 1000}k", m, fm, h0, u0, dt_fine * M, M,
                     extra=dict(dt_fine=dt_fine, spacing_min=float(spacing.min()),
                                spacing_max=float(spacing.max()), H=H))
+
+
+# ---------------------------------------------------------------------------
+# The batched ensemble: 64 members of 10k-400k cells (log-uniform, seeded)
+
+ENS_SEED = 7000
+
+
+def ensemble_sizes(n_members=64, lo=1.0e4, hi=4.0e5, seed=ENS_SEED):
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n_members)).astype(np.int64)
+
+
+def ensemble_member(j, n_cells, iters=3, seed=ENS_SEED) -> Workload:
+    """Member j: the variable-resolution planar family scaled to n_cells,
+    Lloyd-relaxed `iters` times; bump 5(1 + 0.2 z) m, sigma 40(1 + 0.1 z) km,
+    centre jittered by up to 50 km; M drawn from {2, 4, 8}; FP32 state."""
+    rng = np.random.default_rng(seed + j)
+    L = vp.VR_DOMAIN
+    p = vp.sample_points(int(n_cells), L, L, vp.vr_spacing_shape, seed + j)
+    dens = lambda x, y: vp.vr_spacing_shape(x, y) ** -4.0
+    for _ in range(iters):
+        p = vp.lloyd_step(p, L, L, dens)
+    p = vp.morton_sort(p, L)
+    m = vp.periodic_voronoi_mesh(p, L, L, f0=1.0e-4, name=f"member{j}")
+    fm = (vp.vr_spacing_shape(m.xCell, m.yCell) < 0.9 * vp.VR_RATIO).astype(np.uint8)
+    z = rng.standard_normal(2)
+    cx, cy = L / 2 + rng.uniform(-5.0e4, 5.0e4, 2)
+    H = 500.0
+    h0, u0 = gaussian_bump_state(m, H, 5.0 * (1 + 0.2 * z[0]), 4.0e4 * (1 + 0.1 * z[1]), cx, cy)
+    M = int(rng.choice([2, 4, 8]))
+    spacing = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
+    dt_fine = 0.3 * spacing.min() / math.sqrt(9.81 * H)
+    return Workload(f"member{j}", m, fm, h0, u0, dt_fine * M, M,
+                    extra=dict(dt_fine=dt_fine, H=H))
+
+
+def _member_job(args):
+    return ensemble_member(*args)
+
+
+def ensemble_members(n_members=64, iters=3, workers=None, seed=ENS_SEED):
+    """Generate the members in a pool of spawned processes (call before any GPU
+    initialisation in the calling process)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    sizes = ensemble_sizes(n_members, seed=seed)
+    jobs = [(j, int(sizes[j]), iters, seed) for j in range(n_members)]
+    workers = workers or min(16, os.cpu_count() or 1)
+    order = sorted(range(n_members), key=lambda j: -sizes[j])  # big ones first
+    out = [None] * n_members
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = {ex.submit(_member_job, jobs[j]): j for j in order}
+        for f in cf.as_completed(futs):
+            out[futs[f]] = f.result()
+    return out

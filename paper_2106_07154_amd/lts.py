@@ -24,7 +24,10 @@ KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency"]
 EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
             "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_step_scheme", "lts_eval_rhs",
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
-            "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy"]
+            "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
+            "lts_ens_create", "lts_ens_add_member", "lts_ens_init_member", "lts_ens_build",
+            "lts_ens_step", "lts_ens_get_member", "lts_ens_diagnostics", "lts_ens_info",
+            "lts_ens_last_error", "lts_ens_destroy"]
 
 
 class LTSError(RuntimeError):
@@ -96,6 +99,17 @@ def load_library(path: str = LIB_PATH):
         "lts_region_counts": ([P, i64p, i64p, i64p], ci),
         "lts_last_error": ([P], ctypes.c_char_p),
         "lts_destroy": ([P], None),
+        "lts_ens_create": ([PP, ci, ci, P], ci),
+        "lts_ens_add_member": ([P, ctypes.POINTER(_Mesh), P, ci, ci, cd, cd, ci,
+                               ctypes.POINTER(ctypes.c_int)], ci),
+        "lts_ens_init_member": ([P, ci, P, P], ci),
+        "lts_ens_build": ([P, ci], ci),
+        "lts_ens_step": ([P, ci], ci),
+        "lts_ens_get_member": ([P, ci, P, P], ci),
+        "lts_ens_diagnostics": ([P, ci, ctypes.POINTER(_Diag)], ci),
+        "lts_ens_info": ([P, P, P, P, P], ci),
+        "lts_ens_last_error": ([P], ctypes.c_char_p),
+        "lts_ens_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -291,3 +305,83 @@ def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = 
                                      "et_lo", "et_hi"], r[14 + 8 * k: 22 + 8 * k].tolist()))
                      for k, name in enumerate(PASS_NAMES)}
     return out
+
+
+class Ensemble:
+    """Many LTS3 members of uneven size advanced together (lts_ens_* ABI)."""
+
+    def __init__(self, device: int = 0, precision: str = "fp32", stream=None):
+        self._lib = load_library()
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        if stream == 0:
+            raise ValueError("pass a non-default stream")
+        h = ctypes.c_void_p()
+        st = self._lib.lts_ens_create(ctypes.byref(h), int(device),
+                                      {"fp64": LTS_FP64, "fp32": LTS_FP32}[precision],
+                                      ctypes.c_void_p(stream) if stream else None)
+        if st != LTS_OK:
+            raise LTSError(st, "lts_ens_create failed")
+        self._h = h
+        self.meshes = []
+
+    def _check(self, st):
+        if st != LTS_OK:
+            msg = self._lib.lts_ens_last_error(self._h)
+            raise LTSError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lts_ens_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def add_member(self, mesh, fine_mask, dt_coarse, M, n_if1=2, n_if2=2, gravity=9.81,
+                   use_positions=True) -> int:
+        m, keep = _mesh_struct(mesh, use_positions)
+        fm = np.ascontiguousarray(fine_mask, np.uint8)
+        idx = ctypes.c_int()
+        self._check(self._lib.lts_ens_add_member(self._h, ctypes.byref(m), _ptr(fm), int(n_if1),
+                                                 int(n_if2), float(gravity), float(dt_coarse),
+                                                 int(M), ctypes.byref(idx)))
+        self.meshes.append(mesh)
+        return idx.value
+
+    def init_member(self, j, h, u):
+        h = np.ascontiguousarray(h, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        self._check(self._lib.lts_ens_init_member(self._h, int(j), _ptr(h), _ptr(u)))
+
+    def build(self, autotune: bool = True):
+        self._check(self._lib.lts_ens_build(self._h, 1 if autotune else 0))
+
+    def step(self, n_steps: int = 1):
+        self._check(self._lib.lts_ens_step(self._h, int(n_steps)))
+
+    def get_member(self, j):
+        m = self.meshes[j]
+        h = np.empty(m.nCells)
+        u = np.empty(m.nEdges)
+        self._check(self._lib.lts_ens_get_member(self._h, int(j), _ptr(h), _ptr(u)))
+        return h, u
+
+    def diagnostics(self, j) -> Diag:
+        d = _Diag()
+        self._check(self._lib.lts_ens_diagnostics(self._h, int(j), ctypes.byref(d)))
+        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps)
+
+    def info(self):
+        tuned = np.zeros(18, np.int32)
+        us = np.zeros(9)
+        cells = np.zeros(3, np.int64)
+        nl = np.zeros(1, np.int32)
+        self._check(self._lib.lts_ens_info(self._h, _ptr(tuned), _ptr(us), _ptr(cells), _ptr(nl)))
+        names = ["vertex_pv", "cell_tendency", "edge_tendency"]
+        classes = ["small", "medium", "large"]
+        tune = {f"{names[k]}/{classes[s]}": {"block": int(tuned[(k * 3 + s) * 2]),
+                                             "grid_factor": int(tuned[(k * 3 + s) * 2 + 1]),
+                                             "us": round(float(us[k * 3 + s]), 2)}
+                for k in range(3) for s in range(3) if cells[s] > 0}
+        return {"tuning": tune, "class_cells": cells.tolist(), "launches_per_step": int(nl[0])}

@@ -192,9 +192,10 @@ void lts_destroy(lts_ctx *ctx);
    Each member has its own mesh, regions, coarse step dt and ratio M; one
    ensemble step advances every member by one coarse step.  The members'
    passes are batched into shared launches over device work lists (one per
-   phase, kernel class and member size class: < 30k cells, < 120k, larger),
-   the size classes run as concurrent branches of one hipGraph, and an
-   autotuner picks block and grid size per (kernel class, size class).
+   phase, kernel class and member class: size < 30k cells, < 120k, larger,
+   each split by whether some cell has more than 8 edges), the classes run as
+   concurrent branches of one hipGraph, and an autotuner picks block and grid
+   size per (kernel class, member class).
    Results equal lts_step on each member alone (same kernels and arithmetic).
    Call order: create, add_member..., init_member (every member), build,
    step..., get_member / diagnostics, destroy.  Not thread-safe. */
@@ -219,10 +220,12 @@ lts_status lts_ens_diagnostics(lts_ens *ens, int member, lts_diag *out);
 /* Autotuner choices: tuned[(k*3+s)*2 + {0,1}] = block size, grid factor (grid =
    factor x compute units) for kernel class k (0 vertex, 1 cell, 2 edge) and
    size class s; tuned_us[k*3+s] = the timed microseconds of that choice;
-   class_cells[s] = cells per size class; *n_launches = launches per step.
-   Any pointer may be NULL. */
+   class_cells[s] = cells per size class; *n_launches = launches per step;
+   step_bytes[k] = algorithmic bytes of kernel class k in one ensemble step
+   (every array element a launch needs, read or written once).  Any pointer
+   may be NULL. */
 lts_status lts_ens_info(lts_ens *ens, int32_t *tuned, double *tuned_us, int64_t *class_cells,
-                        int32_t *n_launches);
+                        int32_t *n_launches, double *step_bytes);
 const char *lts_ens_last_error(const lts_ens *ens);
 void lts_ens_destroy(lts_ens *ens);
 

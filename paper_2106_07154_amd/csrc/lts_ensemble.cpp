@@ -8,9 +8,10 @@
 // one launch per (phase, kernel class, size class) over a device work list of
 // (member, range, epilogue) items, with a persistent grid that strides over the
 // list's virtual blocks.  Members fall in three size classes (< 30k cells,
-// < 120k, larger); each class is an independent chain of launches on its own
-// stream, and the whole ensemble step is captured once into a hipGraph whose
-// three branches run concurrently.  An autotuner times block size and grid
+// < 120k, larger), each split by slot count (8 or 16 lanes per cell); each
+// class is an independent chain of launches on its own stream, and the whole
+// ensemble step is captured once into a hipGraph whose branches run
+// concurrently.  An autotuner times block size and grid
 // size for every (kernel class, size class) on the members' own data.
 #include <hip/hip_runtime.h>
 
@@ -28,19 +29,27 @@ struct lts_ens {
     lts_precision prec = LTS_FP64;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    hipStream_t side[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    static constexpr int NCLS = 6;  // 3 size classes x 2 slot counts
+    hipStream_t side[NCLS] = {};
+    hipEvent_t fork = nullptr, join[NCLS] = {};
     std::string err;
     std::vector<lts_ctx*> members;
     std::vector<double> dt;
     std::vector<int> M, sclass;
     bool built = false;
-    int G = 0;
     int n_cu = 256;
-    // tuned launch shape per [kernel class][size class]: block size, grid factor
-    int tune_block[KC_N][3] = {{256, 256, 256}, {256, 256, 256}, {256, 256, 256}};
-    int tune_pf[KC_N][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
-    double tune_us[KC_N][3] = {{0}};
+    // tuned launch shape per [kernel class][class]: block size, grid factor
+    int tune_block[KC_N][NCLS];
+    int tune_pf[KC_N][NCLS];
+    double tune_us[KC_N][NCLS] = {};
+    lts_ens() {
+        for (int k = 0; k < KC_N; ++k)
+            for (int c = 0; c < NCLS; ++c) {
+                tune_block[k][c] = 256;
+                tune_pf[k][c] = 4;
+            }
+    }
+    double step_bytes[KC_N] = {0, 0, 0};  // algorithmic bytes of one ensemble step
     struct Launch {
         int sc, kclass, nitems, nvb, block, grid;
         size_t off;  // first item in d_items
@@ -66,7 +75,12 @@ lts_status efail(lts_ens* e, lts_status s, const std::string& msg) {
             return efail(e, LTS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(r_)); \
     } while (0)
 
-int size_class(int n_cells) { return n_cells < 30000 ? 0 : n_cells < 120000 ? 1 : 2; }
+// Class of a member: size class (< 30k cells, < 120k, larger) + 3 when its
+// cells need 16 lanes (more than 8 edges somewhere).
+int member_class(int n_cells, int G) {
+    return (n_cells < 30000 ? 0 : n_cells < 120000 ? 1 : 2) + (G > 8 ? 3 : 0);
+}
+int class_lanes(int cls) { return cls >= 3 ? 16 : 8; }
 
 template <typename T>
 struct Builder {
@@ -116,7 +130,7 @@ struct Builder {
                 w.hi = P.c_hi;
                 w.s0 = r.cs0;
                 w.s1 = r.cs1;
-                n = (long)(P.c_hi - P.c_lo) * e->G;
+                n = (long)(P.c_hi - P.c_lo) * class_lanes(sc);
             } else {
                 w.lo = P.et_lo;
                 w.hi = P.et_hi;
@@ -147,7 +161,7 @@ struct Builder {
         EHIP(e, hipEventCreate(&a));
         EHIP(e, hipEventCreate(&b));
         for (int k = 0; k < KC_N; ++k)
-            for (int sc = 0; sc < 3; ++sc) {
+            for (int sc = 0; sc < lts_ens::NCLS; ++sc) {
                 int best_t = -1, best_n = 0;
                 for (int t = 0; t < nphase; ++t) {
                     const int n = items(t, sc, k, 256, it);
@@ -167,12 +181,13 @@ struct Builder {
                     for (int pf : pfs) {
                         const int grid = std::max(1, std::min(nvb, pf * e->n_cu));
                         const Item<T>* di = static_cast<const Item<T>*>(dbuf);
+                        const int G = class_lanes(sc);
                         for (int w = 0; w < 2; ++w)
-                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, e->G, e->stream));
+                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, G, e->stream));
                         EHIP(e, hipEventRecord(a, e->stream));
                         const int reps = 8;
                         for (int w = 0; w < reps; ++w)
-                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, e->G, e->stream));
+                            EHIP(e, launch_batch<T>(k, di, (int)it.size(), nvb, bs, grid, G, e->stream));
                         EHIP(e, hipEventRecord(b, e->stream));
                         EHIP(e, hipEventSynchronize(b));
                         float ms = 0;
@@ -196,7 +211,15 @@ struct Builder {
     lts_status finalize() {
         std::vector<Item<T>> all, it;
         e->launches.clear();
-        for (int sc = 0; sc < 3; ++sc)
+        for (int k = 0; k < KC_N; ++k) e->step_bytes[k] = 0;
+        for (size_t j = 0; j < recs.size(); ++j)
+            for (const PassRecord<T>& r : recs[j]) {
+                const PassPlan& P = e->members[j]->plan[r.kind];
+                e->step_bytes[KC_VERTEX] += kernel_bytes<T>(P, KC_VERTEX, r.cs0, r.cs1, r.aux);
+                e->step_bytes[KC_CELL] += kernel_bytes<T>(P, KC_CELL, r.cs0, r.cs1, r.aux);
+                e->step_bytes[KC_EDGE] += kernel_bytes<T>(P, KC_EDGE, r.es0, r.es1, r.aux);
+            }
+        for (int sc = 0; sc < lts_ens::NCLS; ++sc)
             for (int t = 0; t < nphase; ++t)
                 for (int k = 0; k < KC_N; ++k) {
                     const int bs = e->tune_block[k][sc];
@@ -221,15 +244,15 @@ struct Builder {
         // capture: fork to one stream per size class, one chain each, join
         EHIP(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipEventRecord(e->fork, e->stream);
-        for (int sc = 0; sc < 3 && err == hipSuccess; ++sc)
+        for (int sc = 0; sc < lts_ens::NCLS && err == hipSuccess; ++sc)
             err = hipStreamWaitEvent(e->side[sc], e->fork, 0);
         const Item<T>* base = static_cast<const Item<T>*>(e->d_items);
         for (const auto& L : e->launches) {
             if (err != hipSuccess) break;
-            err = launch_batch<T>(L.kclass, base + L.off, L.nitems, L.nvb, L.block, L.grid, e->G,
-                                  e->side[L.sc]);
+            err = launch_batch<T>(L.kclass, base + L.off, L.nitems, L.nvb, L.block, L.grid,
+                                  class_lanes(L.sc), e->side[L.sc]);
         }
-        for (int sc = 0; sc < 3 && err == hipSuccess; ++sc) {
+        for (int sc = 0; sc < lts_ens::NCLS && err == hipSuccess; ++sc) {
             err = hipEventRecord(e->join[sc], e->side[sc]);
             if (err == hipSuccess) err = hipStreamWaitEvent(e->stream, e->join[sc], 0);
         }
@@ -298,7 +321,7 @@ lts_status lts_ens_create(lts_ens** out, int device, lts_precision prec, void* h
         ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
         e->own_stream = ok;
     }
-    for (int k = 0; k < 3 && ok; ++k)
+    for (int k = 0; k < lts_ens::NCLS && ok; ++k)
         ok = hipStreamCreateWithFlags(&e->side[k], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&e->join[k], hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) == hipSuccess;
@@ -316,7 +339,7 @@ void lts_ens_destroy(lts_ens* e) {
     if (e->graph) (void)hipGraphDestroy(e->graph);
     if (e->d_items) (void)hipFree(e->d_items);
     for (lts_ctx* c : e->members) lts_destroy(c);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < lts_ens::NCLS; ++k) {
         if (e->side[k]) (void)hipStreamDestroy(e->side[k]);
         if (e->join[k]) (void)hipEventDestroy(e->join[k]);
     }
@@ -341,16 +364,10 @@ lts_status lts_ens_add_member(lts_ens* e, const lts_mesh* mesh, const uint8_t* f
         lts_destroy(c);
         return efail(e, s, "member mesh: " + msg);
     }
-    const int G = padded_slots(c->maxE);
-    if (e->G && G != e->G) {
-        lts_destroy(c);
-        return efail(e, LTS_EMESH, "members must share the slot count (max_edges <= 8 or > 8)");
-    }
-    e->G = G;
     e->members.push_back(c);
     e->dt.push_back(dt_coarse);
     e->M.push_back(M);
-    e->sclass.push_back(size_class(c->nC));
+    e->sclass.push_back(member_class(c->nC, padded_slots(c->maxE)));
     if (member) *member = (int)e->members.size() - 1;
     return LTS_OK;
 }
@@ -411,11 +428,11 @@ lts_status lts_ens_diagnostics(lts_ens* e, int member, lts_diag* out) {
 }
 
 lts_status lts_ens_info(lts_ens* e, int32_t* tuned, double* tuned_us, int64_t* class_cells,
-                        int32_t* n_launches) {
+                        int32_t* n_launches, double* step_bytes) {
     lts_status s = ens_ready(e);
     if (s) return s;
     for (int k = 0; k < KC_N; ++k)
-        for (int sc = 0; sc < 3; ++sc) {
+        for (int sc = 0; sc < 3; ++sc) {  // reported for the 8-lane classes
             if (tuned) {
                 tuned[(k * 3 + sc) * 2] = e->tune_block[k][sc];
                 tuned[(k * 3 + sc) * 2 + 1] = e->tune_pf[k][sc];
@@ -424,9 +441,11 @@ lts_status lts_ens_info(lts_ens* e, int32_t* tuned, double* tuned_us, int64_t* c
         }
     if (class_cells) {
         for (int sc = 0; sc < 3; ++sc) class_cells[sc] = 0;
-        for (size_t j = 0; j < e->members.size(); ++j) class_cells[e->sclass[j]] += e->members[j]->nC;
+        for (size_t j = 0; j < e->members.size(); ++j) class_cells[e->sclass[j] % 3] += e->members[j]->nC;
     }
     if (n_launches) *n_launches = (int32_t)e->launches.size();
+    if (step_bytes)
+        for (int k = 0; k < KC_N; ++k) step_bytes[k] = e->step_bytes[k];
     return LTS_OK;
 }
 

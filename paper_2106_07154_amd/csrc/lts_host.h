@@ -109,6 +109,36 @@ struct PassRecord {
 };
 
 // ---------------------------------------------------------------- launches
+// Algorithmic bytes of one kernel of a pass: every array element the kernel
+// needs, read or written once (T-sized state and coefficients, int32 indices).
+template <typename T>
+double seg_bytes(const Seg<T>& g) {
+    if (!g.mode || g.hi <= g.lo) return 0.0;
+    const double n = g.hi - g.lo;
+    double b = 0.0;
+    if (g.mode == 1) {
+        b = n * sizeof(T) * (1 + (g.xold ? 1 : 0) + (g.xcur ? 1 : 0));
+        if (g.acc) b += n * sizeof(T) * (g.first ? 1 : 2);
+        if (g.mhi > g.mlo) b += (g.mhi - g.mlo) * sizeof(T) * ((g.mnew ? 1 : 0) + (g.mcur ? 1 : 0));
+    } else {
+        b = n * sizeof(T) * (g.first ? 1 : 2);
+    }
+    return b;
+}
+
+template <typename T>
+double kernel_bytes(const PassPlan& P, int kclass, const Seg<T>& s0, const Seg<T>& s1,
+                    const Aux<T>& aux) {
+    const double ts = sizeof(T);
+    if (kclass == KC_VERTEX)
+        return (P.v_hi - P.v_lo) * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts;
+    if (kclass == KC_CELL)
+        return (P.c_hi - P.c_lo) * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
+               (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(s0) + seg_bytes(s1);
+    return (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(s0) + seg_bytes(s1) +
+           (aux.kind == 1 ? 4.0 : aux.kind == 2 ? 3.0 : 0.0) * (aux.nh + aux.nu) * ts;
+}
+
 // Enqueues the passes of one step of a scheme for one context: launches them
 // on stream s (event-stamped when timed), or, when rec is set, records them so
 // the ensemble can batch them with other members' passes.
@@ -139,13 +169,6 @@ struct Run {
         if (timed) c->pending.push_back({cls, a, b, bytes});
     }
 
-    static double seg_bytes(const Seg<T>& g) {
-        if (!g.mode || g.hi <= g.lo) return 0.0;
-        const double n = g.hi - g.lo;
-        if (g.mode == 1) return n * sizeof(T) * (1 + (g.xold ? 1 : 0) + (g.xcur ? 1 : 0));
-        return n * sizeof(T) * (g.first ? 1 : 2);
-    }
-
     // One right-hand-side pass of kind p over state (h, u) with epilogues.
     lts_status pass(int p, const T* h, const T* u, const Seg<T>& cs0, const Seg<T>& cs1,
                     const Seg<T>& es0, const Seg<T>& es1, const Aux<T>& aux = Aux<T>()) {
@@ -156,29 +179,21 @@ struct Run {
         const PassPlan& P = c->plan[p];
         T* q = static_cast<T*>(c->q);
         T* zs = static_cast<T*>(c->zs);
-        const double ts = sizeof(T);
         hipEvent_t e0, e1;
         lts_status st;
         // vertex PV
         if ((st = events(&e0, &e1))) return st;
         HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
-        const double nv = P.v_hi - P.v_lo;
-        done(KC_VERTEX, e0, e1, nv * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts);
+        done(KC_VERTEX, e0, e1, kernel_bytes<T>(P, KC_VERTEX, cs0, cs1, aux));
         // cell tendency + partials
         if ((st = events(&e0, &e1))) return st;
         HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag, s,
                                  e0, e1));
-        const double ncell = P.c_hi - P.c_lo;
-        const double cb = ncell * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
-                          (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(cs0) +
-                          seg_bytes(cs1);
-        done(KC_CELL, e0, e1, cb);
+        done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux));
         // edge tendency (+ appended element-wise job)
         if ((st = events(&e0, &e1))) return st;
         HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1));
-        const double eb = (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(es0) + seg_bytes(es1) +
-                          (aux.kind == 1 ? 4.0 : aux.kind == 2 ? 3.0 : 0.0) * (aux.nh + aux.nu) * ts;
-        done(KC_EDGE, e0, e1, eb);
+        done(KC_EDGE, e0, e1, kernel_bytes<T>(P, KC_EDGE, es0, es1, aux));
         return LTS_OK;
     }
 

@@ -103,18 +103,29 @@ def ensemble_sizes(n_members=64, lo=1.0e4, hi=4.0e5, seed=ENS_SEED):
     return np.exp(rng.uniform(np.log(lo), np.log(hi), n_members)).astype(np.int64)
 
 
-def ensemble_member(j, n_cells, iters=3, seed=ENS_SEED) -> Workload:
+def ensemble_member(j, n_cells, iters=10, seed=ENS_SEED) -> Workload:
     """Member j: the variable-resolution planar family scaled to n_cells,
-    Lloyd-relaxed `iters` times; bump 5(1 + 0.2 z) m, sigma 40(1 + 0.1 z) km,
-    centre jittered by up to 50 km; M drawn from {2, 4, 8}; FP32 state."""
+    Lloyd-relaxed at least `iters` times and then two at a time until every
+    kite area is positive and no cell has more than 8 edges (at most 40
+    iterations); bump 5(1 + 0.2 z) m, sigma 40(1 + 0.1 z) km, centre jittered
+    by up to 50 km; M drawn from {2, 4, 8}."""
     rng = np.random.default_rng(seed + j)
     L = vp.VR_DOMAIN
     p = vp.sample_points(int(n_cells), L, L, vp.vr_spacing_shape, seed + j)
     dens = lambda x, y: vp.vr_spacing_shape(x, y) ** -4.0
-    for _ in range(iters):
-        p = vp.lloyd_step(p, L, L, dens)
-    p = vp.morton_sort(p, L)
-    m = vp.periodic_voronoi_mesh(p, L, L, f0=1.0e-4, name=f"member{j}")
+    done = 0
+    m = None
+    while m is None:
+        for _ in range(iters if done == 0 else 2):
+            p = vp.lloyd_step(p, L, L, dens)
+            done += 1
+        try:
+            m = vp.periodic_voronoi_mesh(vp.morton_sort(p, L), L, L, f0=1.0e-4, name=f"member{j}")
+            if m.maxEdges > 8 and done < 40:
+                m = None
+        except ValueError:
+            if done >= 40:
+                raise
     fm = (vp.vr_spacing_shape(m.xCell, m.yCell) < 0.9 * vp.VR_RATIO).astype(np.uint8)
     z = rng.standard_normal(2)
     cx, cy = L / 2 + rng.uniform(-5.0e4, 5.0e4, 2)
@@ -124,14 +135,14 @@ def ensemble_member(j, n_cells, iters=3, seed=ENS_SEED) -> Workload:
     spacing = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
     dt_fine = 0.3 * spacing.min() / math.sqrt(9.81 * H)
     return Workload(f"member{j}", m, fm, h0, u0, dt_fine * M, M,
-                    extra=dict(dt_fine=dt_fine, H=H))
+                    extra=dict(dt_fine=dt_fine, H=H, lloyd_iterations=done))
 
 
 def _member_job(args):
     return ensemble_member(*args)
 
 
-def ensemble_members(n_members=64, iters=3, workers=None, seed=ENS_SEED):
+def ensemble_members(n_members=64, iters=10, workers=None, seed=ENS_SEED):
     """Generate the members in a pool of spawned processes (call before any GPU
     initialisation in the calling process)."""
     import concurrent.futures as cf

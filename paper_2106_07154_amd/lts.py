@@ -107,7 +107,7 @@ def load_library(path: str = LIB_PATH):
         "lts_ens_step": ([P, ci], ci),
         "lts_ens_get_member": ([P, ci, P, P], ci),
         "lts_ens_diagnostics": ([P, ci, ctypes.POINTER(_Diag)], ci),
-        "lts_ens_info": ([P, P, P, P, P], ci),
+        "lts_ens_info": ([P, P, P, P, P, P], ci),
         "lts_ens_last_error": ([P], ctypes.c_char_p),
         "lts_ens_destroy": ([P], None),
     }
@@ -377,11 +377,14 @@ class Ensemble:
         us = np.zeros(9)
         cells = np.zeros(3, np.int64)
         nl = np.zeros(1, np.int32)
-        self._check(self._lib.lts_ens_info(self._h, _ptr(tuned), _ptr(us), _ptr(cells), _ptr(nl)))
+        by = np.zeros(3)
+        self._check(self._lib.lts_ens_info(self._h, _ptr(tuned), _ptr(us), _ptr(cells), _ptr(nl),
+                                           _ptr(by)))
         names = ["vertex_pv", "cell_tendency", "edge_tendency"]
         classes = ["small", "medium", "large"]
         tune = {f"{names[k]}/{classes[s]}": {"block": int(tuned[(k * 3 + s) * 2]),
                                              "grid_factor": int(tuned[(k * 3 + s) * 2 + 1]),
                                              "us": round(float(us[k * 3 + s]), 2)}
                 for k in range(3) for s in range(3) if cells[s] > 0}
-        return {"tuning": tune, "class_cells": cells.tolist(), "launches_per_step": int(nl[0])}
+        return {"tuning": tune, "class_cells": cells.tolist(), "launches_per_step": int(nl[0]),
+                "step_bytes": {names[k]: float(by[k]) for k in range(3)}}

@@ -12,10 +12,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblts.so")
-SOURCES = [os.path.join(CSRC, "lts_api.cpp"), os.path.join(CSRC, "lts_ensemble.cpp"),
-           os.path.join(CSRC, "lts_kernels.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in ("lts_api.cpp", "lts_ensemble.cpp", "lts_surrogate.cpp",
+                                             "lts_kernels.hip", "lts_mpnn.hip")]
 HEADERS = [os.path.join(CSRC, "lts_internal.h"), os.path.join(CSRC, "lts_host.h"),
-           os.path.join(ROOT, "include", "lts.h")]
+           os.path.join(CSRC, "lts_mpnn.h"), os.path.join(ROOT, "include", "lts.h"),
+           os.path.join(ROOT, "include", "lts_surrogate.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP translation unit.

@@ -27,7 +27,12 @@ EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state"
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
             "lts_ens_create", "lts_ens_add_member", "lts_ens_init_member", "lts_ens_build",
             "lts_ens_step", "lts_ens_get_member", "lts_ens_diagnostics", "lts_ens_info",
-            "lts_ens_last_error", "lts_ens_destroy"]
+            "lts_ens_last_error", "lts_ens_destroy",
+            "lts_sur_create", "lts_sur_info", "lts_sur_node_map", "lts_sur_record",
+            "lts_sur_normalize", "lts_sur_set_norm", "lts_sur_get_norm", "lts_sur_get_params",
+            "lts_sur_set_params", "lts_sur_train", "lts_sur_grad", "lts_sur_features",
+            "lts_sur_predict", "lts_sur_step", "lts_sur_last_error", "lts_sur_destroy",
+            "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16"]
 
 
 class LTSError(RuntimeError):
@@ -110,6 +115,24 @@ def load_library(path: str = LIB_PATH):
         "lts_ens_info": ([P, P, P, P, P, P], ci),
         "lts_ens_last_error": ([P], ctypes.c_char_p),
         "lts_ens_destroy": ([P], None),
+        "lts_sur_create": ([PP, P, ci, ci, ctypes.c_uint64, ci], ci),
+        "lts_sur_info": ([P, P, P, P, P, P], ci),
+        "lts_sur_node_map": ([P, P, P], ci),
+        "lts_sur_record": ([P, cd, ci, ci], ci),
+        "lts_sur_normalize": ([P, ci], ci),
+        "lts_sur_set_norm": ([P, P], ci),
+        "lts_sur_get_norm": ([P, P], ci),
+        "lts_sur_get_params": ([P, P], ci),
+        "lts_sur_set_params": ([P, P], ci),
+        "lts_sur_train": ([P, P, ci, ctypes.c_float, P], ci),
+        "lts_sur_grad": ([P, ci, P, P], ci),
+        "lts_sur_features": ([P, P], ci),
+        "lts_sur_predict": ([P, P, P], ci),
+        "lts_sur_step": ([P, cd, ci, ci, cd, P, P], ci),
+        "lts_sur_last_error": ([P], ctypes.c_char_p),
+        "lts_sur_destroy": ([P], None),
+        "lts_nn_gemm_bf16": ([ci, P, ci, ci, P, P, P], ci),
+        "lts_nn_gemm_tn_bf16": ([ci, P, ci, ci, P, P], ci),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -388,3 +411,143 @@ class Ensemble:
                 for k in range(3) for s in range(3) if cells[s] > 0}
         return {"tuning": tune, "class_cells": cells.tolist(), "launches_per_step": int(nl[0]),
                 "step_bytes": {names[k]: float(by[k]) for k in range(3)}}
+
+
+# ---------------------------------------------------------------------------
+# Learned fine-region surrogate (include/lts_surrogate.h)
+
+N_FEATURES = 16
+
+
+class Surrogate:
+    """A message-passing surrogate attached to an LTSContext (mesh and state
+    set).  Arrays are numpy; node order is the library's (see node_map)."""
+
+    def __init__(self, ctx: LTSContext, seed: int = 0, max_samples: int = 0, n_layers: int = 3,
+                 hidden: int = 64):
+        self._lib = load_library()
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        st = self._lib.lts_sur_create(ctypes.byref(h), ctx._h, int(n_layers), int(hidden),
+                                      ctypes.c_uint64(seed), int(max_samples))
+        if st != LTS_OK:
+            msg = self._lib.lts_last_error(ctx._h)
+            raise LTSError(st, msg.decode() if msg else "")
+        self._h = h
+        v = np.zeros(5, np.int32)
+        self._check(self._lib.lts_sur_info(self._h, *[_ptr(v[i:i + 1]) for i in range(5)]))
+        self.n_nodes, self.n_fine_cells, self.n_fine_edges, self.n_params = (int(x) for x in v[:4])
+
+    def _check(self, st):
+        if st != LTS_OK:
+            msg = self._lib.lts_sur_last_error(self._h)
+            raise LTSError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lts_sur_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def n_samples(self) -> int:
+        v = np.zeros(1, np.int32)
+        self._check(self._lib.lts_sur_info(self._h, None, None, None, None, _ptr(v)))
+        return int(v[0])
+
+    def node_map(self):
+        nc = np.empty(self.n_nodes, np.int32)
+        fe = np.empty(self.n_fine_edges, np.int32)
+        self._check(self._lib.lts_sur_node_map(self._h, _ptr(nc), _ptr(fe)))
+        return nc, fe
+
+    def record(self, dt: float, M: int, n_steps: int):
+        self._check(self._lib.lts_sur_record(self._h, float(dt), int(M), int(n_steps)))
+
+    def normalize(self, n_samples: int | None = None):
+        n = self.n_samples if n_samples is None else n_samples
+        self._check(self._lib.lts_sur_normalize(self._h, int(n)))
+
+    def set_norm(self, norm):
+        a = np.ascontiguousarray(norm, np.float32)
+        assert a.size == 16
+        self._check(self._lib.lts_sur_set_norm(self._h, _ptr(a)))
+
+    def get_norm(self):
+        a = np.empty(16, np.float32)
+        self._check(self._lib.lts_sur_get_norm(self._h, _ptr(a)))
+        return a
+
+    def get_params(self):
+        a = np.empty(self.n_params, np.float32)
+        self._check(self._lib.lts_sur_get_params(self._h, _ptr(a)))
+        return a
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        assert a.size == self.n_params
+        self._check(self._lib.lts_sur_set_params(self._h, _ptr(a)))
+
+    def train(self, idx, lr: float = 1e-3):
+        idx = np.ascontiguousarray(idx, np.int32)
+        losses = np.empty(idx.size, np.float32)
+        self._check(self._lib.lts_sur_train(self._h, _ptr(idx), int(idx.size), ctypes.c_float(lr),
+                                            _ptr(losses)))
+        return losses
+
+    def grad(self, k: int):
+        loss = np.empty(1, np.float32)
+        g = np.empty(self.n_params, np.float32)
+        self._check(self._lib.lts_sur_grad(self._h, int(k), _ptr(loss), _ptr(g)))
+        return float(loss[0]), g
+
+    def features(self):
+        a = np.empty((self.n_nodes, N_FEATURES), np.float32)
+        self._check(self._lib.lts_sur_features(self._h, _ptr(a)))
+        return a
+
+    def predict(self):
+        oh = np.empty(self.n_fine_cells, np.float32)
+        ou = np.empty(self.n_fine_edges, np.float32)
+        self._check(self._lib.lts_sur_predict(self._h, _ptr(oh), _ptr(ou)))
+        return oh, ou
+
+    def step(self, dt: float, M: int, n_steps: int = 1, tau: float = 0.0):
+        acc = np.zeros(1, np.int32)
+        res = np.empty(max(n_steps, 1))
+        self._check(self._lib.lts_sur_step(self._h, float(dt), int(M), int(n_steps), float(tau),
+                                           _ptr(acc), _ptr(res)))
+        return int(acc[0]), res[:n_steps]
+
+
+def nn_gemm_bf16(A_bits, W_bits, bias=None, device: int = 0):
+    """Y = A W (+ bias) on the matrix cores; A [N x K], W [K x 64] as BF16 bit
+    patterns (uint16); returns FP32 [N x 64]."""
+    lib = load_library()
+    A = np.ascontiguousarray(A_bits, np.uint16)
+    W = np.ascontiguousarray(W_bits, np.uint16)
+    N, K = A.shape
+    assert W.shape == (K, 64)
+    Y = np.empty((N, 64), np.float32)
+    b = None if bias is None else np.ascontiguousarray(bias, np.float32)
+    st = lib.lts_nn_gemm_bf16(int(device), _ptr(A), N, K, _ptr(W), None if b is None else _ptr(b),
+                              _ptr(Y))
+    if st != LTS_OK:
+        raise LTSError(st, "lts_nn_gemm_bf16")
+    return Y
+
+
+def nn_gemm_tn_bf16(A_bits, D_bits, device: int = 0):
+    """P = A^T D on the matrix cores; A [N x K], D [N x 64] BF16 bit patterns."""
+    lib = load_library()
+    A = np.ascontiguousarray(A_bits, np.uint16)
+    D = np.ascontiguousarray(D_bits, np.uint16)
+    N, K = A.shape
+    assert D.shape == (N, 64)
+    P = np.empty((K, 64), np.float32)
+    st = lib.lts_nn_gemm_tn_bf16(int(device), _ptr(A), N, K, _ptr(D), _ptr(P))
+    if st != LTS_OK:
+        raise LTSError(st, "lts_nn_gemm_tn_bf16")
+    return P

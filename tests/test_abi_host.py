@@ -27,7 +27,8 @@ def lib():
 
 
 def test_exports_every_declared_symbol(lib):
-    text = open(os.path.join(ROOT, "include", "lts.h")).read()
+    import glob
+    text = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     decl = re.compile(r"^(?:lts_status|void|int|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
                       re.M)
     declared = sorted(set(decl.findall(text)))

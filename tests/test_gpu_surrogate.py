@@ -1,0 +1,286 @@
+"""GPU checks of the learned fine-region surrogate, through the C ABI, against
+the FP64 reference network (oracle/mpnn.py) and the FP64 solver oracle.
+
+Tolerances.  The matrix-core GEMMs take BF16 inputs and accumulate in FP32:
+|Y - Y_exact| <= K 2^-24 sum_k |a_k w_k| per entry (held at 4x that).  The
+network keeps activations in BF16: every layer output, neighbour mean and
+input feature is rounded to 8 significant bits (relative error <= 2^-9).
+With 9 such roundings on the forward path, errors of random sign and a
+depth-3 ReLU network that roughly preserves relative size, the expected
+relative L2 error of the outputs is ~ sqrt(9) 2^-9 / sqrt(3) ~ 3.4e-3; the
+bound used is 2e-2.  The backward pass adds a BF16 rounding of every dZ: the
+per-block relative L2 error of the gradient is held to 4e-2.  Weights given
+to both sides are BF16-representable, so weight rounding is not part of the
+error.  Everything that is not network arithmetic (node set, fine edges,
+features, the surrogate step's SSPRK3 stages on I u C and its trapezoid
+residual) is FP64 in an FP64 context and held to the solver's own 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import F, I1, I2, Oracle
+from oracle import mpnn
+from paper_2106_07154_amd import lts
+from paper_2106_07154_amd.inputs import gaussian_bump_state, igw_parameters, igw_state, strip_fine_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return math.sqrt(float(np.sum((np.asarray(a, np.float64) - b) ** 2)) /
+                     max(float(np.sum(np.asarray(b, np.float64) ** 2)), 1e-300))
+
+
+def bf16_bits(x):
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return ((b + 0x7FFF + ((b >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def bf16_round(x):
+    return (bf16_bits(x).astype(np.uint32) << 16).view(np.float32)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lts.load_library()
+
+
+# ------------------------------------------------------------------ GEMMs
+@pytest.mark.parametrize("N,K", [(200, 16), (333, 128), (64, 64), (1, 32)])
+def test_mfma_gemm_layout(N, K):
+    say("gemm", N, K)
+    rng = np.random.default_rng(N * 1000 + K)
+    A = bf16_round(rng.standard_normal((N, K)))
+    W = bf16_round(rng.standard_normal((K, 64)) / math.sqrt(K))
+    b = rng.standard_normal(64).astype(np.float32)
+    Y = lts.nn_gemm_bf16(bf16_bits(A), bf16_bits(W), b)
+    ref = A.astype(np.float64) @ W.astype(np.float64) + b
+    bound = 4 * K * 2.0 ** -24 * (np.abs(A).astype(np.float64) @ np.abs(W) + np.abs(b)) + 1e-30
+    assert np.all(np.abs(Y - ref) <= bound)
+
+
+@pytest.mark.parametrize("N,K", [(1000, 128), (37, 16), (1100, 64)])
+def test_mfma_gemm_tn_layout(N, K):
+    say("gemm_tn", N, K)
+    rng = np.random.default_rng(N + K)
+    A = bf16_round(rng.standard_normal((N, K)))
+    D = bf16_round(rng.standard_normal((N, 64)))
+    P = lts.nn_gemm_tn_bf16(bf16_bits(A), bf16_bits(D))
+    ref = A.astype(np.float64).T @ D.astype(np.float64)
+    bound = 4 * N * 2.0 ** -24 * (np.abs(A).astype(np.float64).T @ np.abs(D)) + 1e-30
+    assert np.all(np.abs(P - ref) <= bound)
+
+
+# ------------------------------------------------------------ network parity
+def _lloyd_case(lloyd_mesh):
+    m = lloyd_mesh
+    fm = (np.hypot(m.xCell - 2e5, m.yCell - 2e5) < 5e4).astype(np.uint8)
+    h, u = gaussian_bump_state(m, 500.0, 5.0, 4.0e4, 2.1e5, 1.9e5)
+    return m, fm, h, u
+
+
+def _test_params(seed):
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, s in mpnn.param_shapes():
+        fan = s[0] if len(s) == 2 else 64
+        P[name] = rng.standard_normal(s) * (math.sqrt(2.0 / fan) if len(s) == 2 else 0.1)
+    return bf16_round(mpnn.pack(P)).astype(np.float64)
+
+
+def _norm_from(raw, th, tu):
+    mu = raw[:, :5].mean(axis=0)
+    sd = raw[:, :5].std(axis=0)
+    inv = np.where(sd > 1e-5 * (np.abs(mu) + 1e-30), 1.0 / np.maximum(sd, 1e-300), 0.0)
+    rh = math.sqrt(np.mean(th ** 2)) or 1.0
+    ru = math.sqrt(np.mean(tu ** 2)) or 1.0
+    n = np.zeros(16)
+    n[:5], n[5:10], n[10], n[11], n[12], n[13] = mu, inv, 1 / rh, 1 / ru, rh, ru
+    return n.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def lloyd_setup(lloyd_mesh):
+    m, fm, h, u = _lloyd_case(lloyd_mesh)
+    o = Oracle(m)
+    reg = o.regions(fm, 2, 2)
+    ctx = lts.LTSContext(0, "fp64")
+    ctx.upload_mesh(m, fm, 2, 2)
+    ctx.init_state(h, u)
+    sur = lts.Surrogate(ctx, seed=1, max_samples=4)
+    nodes, fedges = sur.node_map()
+    G = mpnn.build_graph(m, reg, node_order=nodes, edge_order=fedges)
+    return dict(m=m, fm=fm, h=h, u=u, o=o, reg=reg, ctx=ctx, sur=sur, G=G)
+
+
+def test_node_set_and_features(lloyd_setup):
+    S = lloyd_setup
+    m, reg, sur, G = S["m"], S["reg"], S["sur"], S["G"]
+    say("surrogate node set / features", m.nCells)
+    nodes, fedges = sur.node_map()
+    want = np.flatnonzero((reg.cell == F) | (reg.cell == I1) | (reg.cell == I2))
+    assert sorted(nodes.tolist()) == want.tolist()
+    assert np.all(reg.cell[nodes[:sur.n_fine_cells]] == F)
+    assert np.all(reg.cell[nodes[sur.n_fine_cells:]] != F)
+    assert sorted(fedges.tolist()) == np.flatnonzero(reg.edge == F).tolist()
+    raw = sur.features()
+    ref = mpnn.raw_features(m, S["o"], reg, S["h"], S["u"], nodes)
+    for f in range(16):
+        scale = max(np.abs(ref[:, f]).max(), 1e-30)
+        err = np.abs(raw[:, f] - ref[:, f])
+        assert np.all(err <= 2 ** -23 * np.abs(ref[:, f]) + 1e-6 * scale), f
+
+
+def test_forward_parity(lloyd_setup):
+    S = lloyd_setup
+    sur, G = S["sur"], S["G"]
+    say("surrogate forward parity")
+    p = _test_params(11)
+    ref_raw = mpnn.raw_features(S["m"], S["o"], S["reg"], S["h"], S["u"], G.nodes)
+    norm = _norm_from(ref_raw, np.ones(3), np.ones(3))
+    norm[:5] = bf16_round(norm[:5])
+    sur.set_params(p.astype(np.float32))
+    sur.set_norm(norm)
+    oh, ou = sur.predict()
+    X = mpnn.normalise(ref_raw, norm.astype(np.float64))
+    rh, ru, _ = mpnn.forward(p, G, X)
+    say("forward rel L2", rel_l2(oh, rh), rel_l2(ou, ru))
+    assert rel_l2(oh, rh) < 2e-2 and rel_l2(ou, ru) < 2e-2
+
+
+def test_gradient_parity(lloyd_setup):
+    S = lloyd_setup
+    sur, G, o, ctx = S["sur"], S["G"], S["o"], S["ctx"]
+    say("surrogate gradient parity")
+    m = S["m"]
+    dt = 0.3 * 3.0e3 / math.sqrt(9.81 * 500.0) * 4
+    ctx.init_state(S["h"], S["u"])
+    sur.record(dt, 4, 1)
+    h1, u1 = o.lts(S["h"], S["u"], dt, 4, S["reg"], n=1)
+    th = (h1 - S["h"])[G.nodes[:G.fine]]
+    tu = (u1 - S["u"])[G.edges]
+    ref_raw = mpnn.raw_features(m, o, S["reg"], S["h"], S["u"], G.nodes)
+    norm = _norm_from(ref_raw, th, tu)
+    p = _test_params(12)
+    sur.set_params(p.astype(np.float32))
+    sur.set_norm(norm)
+    loss, g = sur.grad(0)
+    X = mpnn.normalise(ref_raw, norm.astype(np.float64))
+    rl, rg = mpnn.loss_and_grad(p, G, X, th * float(norm[10]), tu * float(norm[11]))
+    say("loss", loss, rl)
+    assert abs(loss - rl) <= 2e-2 * rl
+    off = 0
+    for name, s in mpnn.param_shapes():
+        n = int(np.prod(s))
+        e = rel_l2(g[off:off + n], rg[off:off + n])
+        say("grad", name, e)
+        assert e < 4e-2, name
+        off += n
+
+
+# --------------------------------------------------------- step and the gate
+@pytest.fixture(scope="module")
+def igw():
+    from paper_2106_07154_amd.inputs.workloads import igw_hex
+    return igw_hex()
+
+
+def _ctx(w, prec="fp64"):
+    c = lts.LTSContext(0, prec)
+    c.upload_mesh(w.mesh, w.fine_mask, w.n_if1, w.n_if2)
+    c.init_state(w.h0, w.u0)
+    return c
+
+
+def test_zero_network_step_matches_oracle(igw):
+    """All-zero parameters predict no change on F: the surrogate step is then
+    SSPRK3 on I u C with F frozen, and r = ||(R(x_n) + R(x_new))/2|| /
+    ||R(x_n)|| on F; both follow from the oracle's right-hand side."""
+    w = igw
+    say("zero-network surrogate step", w.name)
+    c = _ctx(w)
+    sur = lts.Surrogate(c, seed=0)
+    sur.set_params(np.zeros(sur.n_params, np.float32))
+    sur.set_norm(np.array([0] * 5 + [1] * 9 + [0, 0], np.float32))
+    acc, res = sur.step(w.dt_coarse, w.M, 1, tau=1e30)
+    assert acc == 1
+    h, u = c.get_state()
+    o = Oracle(w.mesh)
+    reg = o.regions(w.fine_mask, w.n_if1, w.n_if2)
+    fc, fe = reg.cell == F, reg.edge == F
+    x0h, x0u, dt = w.h0, w.u0, w.dt_coarse
+
+    def stage(xh, xu, baseh, baseu, a, b):
+        dh, du = o.rhs(xh, xu)
+        nh = a * baseh + b * (xh + dt * dh)
+        nu = a * baseu + b * (xu + dt * du)
+        nh[fc], nu[fe] = x0h[fc], x0u[fe]
+        return nh, nu
+
+    y1 = stage(x0h, x0u, x0h, x0u, 0.0, 1.0)
+    y2 = stage(*y1, x0h, x0u, 0.75, 0.25)
+    y3 = stage(*y2, x0h, x0u, 1.0 / 3.0, 2.0 / 3.0)
+    assert np.array_equal(h[fc], x0h[fc]) and np.array_equal(u[fe], x0u[fe])
+    assert rel_l2(h, y3[0]) < 1e-12 and rel_l2(u - x0u, y3[1] - x0u) < 1e-10
+    R0 = o.rhs(x0h, x0u)
+    R1 = o.rhs(*y3)
+    rh = np.linalg.norm(0.5 * (R0[0] + R1[0])[fc]) / np.linalg.norm(R0[0][fc])
+    ru = np.linalg.norm(0.5 * (R0[1] + R1[1])[fe]) / np.linalg.norm(R0[1][fe])
+    say("residual", res[0], max(rh, ru))
+    assert abs(res[0] - max(rh, ru)) <= 1e-10 * max(rh, ru)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gate_rejects_fall_back_to_lts3_bitwise(igw, prec):
+    w = igw
+    say("surrogate fallback", prec)
+    a, b = _ctx(w, prec), _ctx(w, prec)
+    sur = lts.Surrogate(a, seed=3)
+    sur.set_norm(np.array([0] * 5 + [1] * 9 + [0, 0], np.float32))
+    acc, res = sur.step(w.dt_coarse, w.M, 3, tau=0.0)     # tau = 0 rejects every step
+    assert acc == 0 and res.shape == (3,)
+    p = sur.get_params()
+    p[-1] = np.nan            # corrupted head bias (ReLU maps a NaN inside the net to 0)
+    sur.set_params(p)
+    acc2, res2 = sur.step(w.dt_coarse, w.M, 2, tau=1e30)
+    assert acc2 == 0 and not np.any(np.isfinite(res2))
+    b.step(w.dt_coarse, w.M, 5)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da.n_nonfinite == 0 and da.steps == db.steps == 5 and da.t == db.t
+
+
+def test_training_reduces_loss_and_gate_accepts(igw):
+    w = igw
+    say("surrogate training", w.name)
+    c = _ctx(w)
+    sur = lts.Surrogate(c, seed=5, max_samples=40)
+    sur.record(w.dt_coarse, w.M, 40)
+    sur.normalize()
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, 32, 600)
+    losses = sur.train(idx, lr=2e-3)
+    say("loss first/last", losses[:10].mean(), losses[-50:].mean())
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() < 0.2 * losses[:10].mean()
+    # held-out samples 32..39 are never trained on: their loss stays bounded
+    held = [sur.grad(k)[0] for k in range(32, 40)]
+    assert np.all(np.isfinite(held))
+    # gated steps from the recorded end state: with a loose tau they are kept
+    acc, res = sur.step(w.dt_coarse, w.M, 4, tau=1e30)
+    assert acc == 4 and np.all(np.isfinite(res))
+    d = c.diagnostics()
+    assert d.n_nonfinite == 0 and d.steps == 44

@@ -56,7 +56,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["vr", "igw", "ensemble"], default="vr")
+    ap.add_argument("--workload", choices=["vr", "igw", "ensemble", "surrogate"], default="vr")
+    ap.add_argument("--trajectories", type=int, default=10,
+                    help="surrogate: seeded training trajectories (the last 2 held out)")
+    ap.add_argument("--traj-steps", type=int, default=200, help="surrogate: steps per trajectory")
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate: training epochs")
     ap.add_argument("--members", type=int, default=64, help="ensemble members")
     ap.add_argument("--lloyd", type=int, default=10,
                     help="minimum Lloyd iterations per ensemble member")
@@ -66,12 +70,15 @@ def main():
                     help="LTS3 FP64 timed region only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(every box here has a single MI355X); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(the sharded design is documented, not built); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "ensemble":
         return bench_ensemble(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     import numpy as np
     import torch
     from paper_2106_07154_amd.build import LIB
@@ -292,6 +299,165 @@ def bench_ensemble(args):
                                 "l2_height_error_sampled": errs,
                                 "reference": "FP64 SSPRK3 at a quarter of each member's fine step"}}
     ens.close()
+    print(json.dumps(out), flush=True)
+
+
+
+def bench_surrogate(args):
+    """The learned fine-region surrogate on the 200k variable-resolution mesh:
+    record LTS3 trajectories (seeded bumps), train, calibrate the gate on a
+    held-out trajectory, then time gated and ungated surrogate runs and plain
+    LTS3 at 1-4x the coarse step on another held-out trajectory against an
+    FP64 SSPRK3 reference at a quarter of the fine step."""
+    import numpy as np
+    import torch
+    from paper_2106_07154_amd import lts
+    from paper_2106_07154_amd.inputs import workloads
+
+    w = workloads.vr_planar()
+    m, M, dt = w.mesh, w.M, w.dt_coarse
+    K = args.steps - args.steps % 12 if args.steps >= 12 else 12
+    n_traj, n_steps = args.trajectories, args.traj_steps
+    n_hold = 2
+    n_train = (n_traj - n_hold) * n_steps
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    init = lambda i: workloads.surrogate_initial_state(m, i)
+
+    def make(prec="fp64", i=0):
+        c = lts.LTSContext(0, prec, stream=sp)
+        c.upload_mesh(m, w.fine_mask, w.n_if1, w.n_if2, w.gravity)
+        c.init_state(*init(i))
+        return c
+
+    ctx = make()
+    sur = lts.Surrogate(ctx, seed=2106, max_samples=n_traj * n_steps)
+    log(f"surrogate: {sur.n_nodes} nodes, {sur.n_fine_cells} fine cells, "
+        f"{sur.n_fine_edges} fine edges, {sur.n_params} parameters")
+    t0 = time.time()
+    for i in range(n_traj):
+        ctx.init_state(*init(i))
+        sur.record(dt, M, n_steps)
+    t_rec = time.time() - t0
+    sur.normalize(n_train)
+    log(f"recorded {sur.n_samples} samples in {t_rec:.1f}s; norm {sur.get_norm().round(5).tolist()}")
+    rng = np.random.default_rng(1)
+    t0 = time.time()
+    hist = []
+    for ep in range(args.epochs):
+        lr = 1e-3 * (0.5 * (1 + math.cos(math.pi * ep / args.epochs)) * 0.9 + 0.1)
+        losses = sur.train(rng.permutation(n_train).astype(np.int32), lr=lr)
+        hist.append(float(losses.mean()))
+        log(f"epoch {ep}: lr {lr:.2e} mean loss {hist[-1]:.4e}")
+    t_train = time.time() - t0
+    iters = args.epochs * n_train
+    held = [sur.grad(k)[0] for k in range(n_train, n_traj * n_steps, 10)]
+    log(f"training {t_train:.1f}s ({t_train / iters * 1e3:.3f} ms/iteration); held-out loss "
+        f"{np.mean(held):.4e}")
+
+    # gate calibration on held-out trajectory n_traj - 2: the surrogate's
+    # residual (every step rejected, so the state follows plain LTS3) and
+    # LTS3's own trapezoid residual at the same states
+    reg = ctx.regions()
+    fc, fe = reg[0] == 3, reg[1] == 3
+
+    def trap(x0, x1, R0, R1, mask):
+        r = (x1 - x0)[mask] / dt - 0.5 * (R0 + R1)[mask]
+        den = 0.5 * (np.linalg.norm(R0[mask]) + np.linalg.norm(R1[mask]))
+        return float(np.linalg.norm(r) / den)
+
+    ctx.init_state(*init(n_traj - 2))
+    r_sur, r_lts = [], []
+    x0 = ctx.get_state()
+    R0 = ctx.eval_rhs(*x0)
+    for k in range(24):
+        _, res = sur.step(dt, M, 1, tau=-1.0)
+        r_sur.append(float(res[0]))
+        x1 = ctx.get_state()
+        R1 = ctx.eval_rhs(*x1)
+        r_lts.append(max(trap(x0[0], x1[0], R0[0], R1[0], fc), trap(x0[1], x1[1], R0[1], R1[1], fe)))
+        x0, R0 = x1, R1
+    tau = 3.0 * max(r_lts)
+    log(f"gate calibration: LTS3 residual median {np.median(r_lts):.3e} max {max(r_lts):.3e}; "
+        f"surrogate residual median {np.median(r_sur):.3e} min {min(r_sur):.3e}; tau {tau:.3e}")
+
+    # evaluation on held-out trajectory n_traj - 1
+    ev = n_traj - 1
+    ref = make("fp64", ev)
+    ref.step_rk3(dt / (4 * M), K * M * 4)
+    h_ref, _ = ref.get_state()
+    ref.close()
+    h_init, _ = init(ev)
+    H = float(np.median(h_init))
+    wA = m.areaCell
+    err = lambda h: rel_l2(h - H, h_ref - H, wA) if np.all(np.isfinite(h)) else float("inf")
+    runs = {}
+    for kk in (1, 2, 3, 4):
+        c = make("fp64", ev)
+        c.step(kk * dt, M, 1)
+        c.init_state(*init(ev))
+        ms = timed(torch, stream, lambda: c.step(kk * dt, M, K // kk))
+        h, _ = c.get_state()
+        runs[f"lts3_dt_x{kk}"] = {"ms": round(ms, 3), "err": err(h)}
+        c.close()
+        log(f"LTS3 dt x{kk}: {ms:.2f} ms, err {runs[f'lts3_dt_x{kk}']['err']:.3e}")
+    for name, t, bo in (("surrogate_gated", tau, 64), ("surrogate_ungated", 1e30, 0)):
+        ctx.init_state(*init(ev))
+        sur.step(dt, M, 1, tau=-1.0)   # capture / warm the graphs, clear the back-off
+        ctx.init_state(*init(ev))
+        d0 = ctx.diagnostics()
+        acc = [0]
+        resid = []
+
+        def run():
+            a, r = sur.step(dt, M, K, tau=t, max_backoff=bo)
+            acc[0] = a
+            resid.append(r)
+        try:
+            ms = timed(torch, stream, run)
+            d1 = ctx.diagnostics()
+            h, _ = ctx.get_state()
+            runs[name] = {"ms": round(ms, 3), "err": err(h), "accepted": acc[0], "steps": K,
+                          "tau": t if t < 1e29 else None,
+                          "mass_rel_defect": abs(d1.mass - d0.mass) / d0.mass,
+                          "max_backoff": bo,
+                          "residual_median": float(np.median(resid[0][resid[0] >= 0]))}
+        except lts.LTSError as ex:   # the run left finite values behind
+            runs[name] = {"ms": None, "err": float("inf"), "accepted": acc[0], "steps": K,
+                          "tau": t if t < 1e29 else None, "diverged": str(ex)}
+            log(f"{name}: diverged ({ex})")
+            continue
+        log(f"{name}: {ms:.2f} ms, accepted {acc[0]}/{K}, err {runs[name]['err']:.3e}, "
+            f"mass defect {runs[name]['mass_rel_defect']:.2e}")
+    base = runs["lts3_dt_x1"]
+    g = runs["surrogate_gated"]
+    eps = g["err"]
+    ok = [v["ms"] for k, v in runs.items() if k.startswith("lts3") and v["err"] <= eps]
+    best = min(ok) if ok else None
+    g_ms = g["ms"] or float("inf")
+    value = m.nCells * M * K / (g_ms / 1e3)
+    out = {"metric": "cell-updates/s of the gated surrogate step; time-to-solution vs plain LTS3 "
+                     "at the surrogate's L2 height error",
+           "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
+           "warmup": 1, "ms_per_step": round(g_ms / K, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+           "config": {"workload": f"surrogate-{w.name}", "cells": m.nCells, "M": M,
+                      "nodes": sur.n_nodes, "fine_cells": sur.n_fine_cells,
+                      "fine_edges": sur.n_fine_edges, "params": sur.n_params,
+                      "trajectories": n_traj, "held_out": n_hold, "traj_steps": n_steps,
+                      "epochs": args.epochs},
+           "training": {"record_s": round(t_rec, 2), "train_s": round(t_train, 2),
+                        "ms_per_iteration": round(t_train / iters * 1e3, 4),
+                        "epoch_loss": [round(x, 5) for x in hist], "held_out_loss": float(np.mean(held))},
+           "gate": {"tau": tau, "rule": "3 x max LTS3 trapezoid residual on a held-out trajectory",
+                    "lts3_residual_median": float(np.median(r_lts)),
+                    "surrogate_residual_median": float(np.median(r_sur))},
+           "runs": runs,
+           "gain_same_dt": round(base["ms"] / g_ms, 3),
+           "gain_time_to_solution": round(best / g_ms, 3) if best else None,
+           "epsilon": eps}
+    sur.close()
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -15,8 +15,10 @@
  *                                               l = 1, 2, 3, Wl [128 x 64]
  *   out_h[i] = H3[i] . wh + bh                   fine cells i
  *   out_u[e] = (H3[c1(e)] - H3[c0(e)]) . wu      fine edges e, normal c0 -> c1
- * and the predicted increments over one coarse step are
- *   dh = rms_h * out_h,  du = rms_u * out_u.
+ * and the prediction of the state on F one coarse step dt ahead is a
+ * forward-Euler step plus the network's correction,
+ *   h + dt R_h(x_n) + rms_h * out_h,  u + dt R_u(x_n) + rms_u * out_u,
+ * with R the right-hand side of eq:sweTimeStepping.
  * Weights and activations are BF16 with FP32 accumulation on the matrix
  * cores; biases, head weights and the Adam state are FP32.
  *
@@ -62,9 +64,10 @@ lts_status lts_sur_info(const lts_sur *s, int *n_nodes, int *n_fine_cells, int *
 lts_status lts_sur_node_map(const lts_sur *s, int32_t *node_cell, int32_t *fine_edge);
 
 /* Training data from the solver itself: n_steps times, store the raw
-   features of the context state, advance it one plain LTS3 coarse step
-   (Algorithm 2.2, dt, M) and store the increments of h on the fine cells and
-   u on the fine edges.  Advances the context by n_steps. */
+   features of the context state x_n, advance it one plain LTS3 coarse step
+   (Algorithm 2.2, dt, M) and store the correction targets
+   x_{n+1} - x_n - dt R(x_n) of h on the fine cells and u on the fine edges.
+   Advances the context by n_steps. */
 lts_status lts_sur_record(lts_sur *s, double dt, int M, int n_steps);
 
 /* Compute the normalisation vector from samples 0 .. n_samples-1 (feature
@@ -79,7 +82,8 @@ lts_status lts_sur_set_params(lts_sur *s, const float *p);
 
 /* n_iters Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8), step i on the
    recorded sample idx[i].  Loss per step = mean over fine cells of
-   (out_h - dh/rms_h)^2 + mean over fine edges of (out_u - du/rms_u)^2;
+   (out_h - th/rms_h)^2 + mean over fine edges of (out_u - tu/rms_u)^2 with
+   (th, tu) the sample's correction targets;
    losses[i] (may be NULL) receives it.  Synchronises. */
 lts_status lts_sur_train(lts_sur *s, const int32_t *idx, int n_iters, float lr, float *losses);
 
@@ -103,13 +107,19 @@ lts_status lts_sur_predict(lts_sur *s, float *out_h, float *out_u);
    one SSPRK3 step of size dt (Algorithm 2.1) on the Step-2 pass set, reading
    F at t, t + dt and t + dt/2 as x_n, the prediction and their mean; then
      r = max over (h on fine cells, u on fine edges) of
-         || (x_pred - x_n)/dt - (R(x_n) + R(x_pred))/2 || / || R(x_n) ||
-   (trapezoid residual; R the right-hand side of eq:sweTimeStepping).  A step
-   with r < tau is kept, any other is recomputed from x_n by the plain LTS3
-   step (dt, M).  n_accepted and residuals[n_steps] (either may be NULL)
-   report the outcome.  Synchronises once per step. */
-lts_status lts_sur_step(lts_sur *s, double dt, int M, int n_steps, double tau, int *n_accepted,
-                        double *residuals);
+         || (x_pred - x_n)/dt - (R(x_n) + R(x_pred))/2 ||
+         / ((|| R(x_n) || + || R(x_pred) ||) / 2)
+   (the trapezoid-rule defect of the step; L2 norms over the fine cells or
+   fine edges).  A step with r < tau is kept, any other (r NaN included) is
+   recomputed from x_n by the plain LTS3 step (dt, M).  With max_backoff > 0
+   a rejection also skips the surrogate for the next b steps (plain LTS3),
+   b doubling with every further rejection up to max_backoff and resetting on
+   an acceptance; the back-off state persists across calls.  max_backoff = 0
+   tries the surrogate on every step.  n_accepted and residuals[n_steps]
+   (-1 for a skipped step; either may be NULL) report the outcome.
+   Synchronises once per attempted step. */
+lts_status lts_sur_step(lts_sur *s, double dt, int M, int n_steps, double tau, int max_backoff,
+                        int *n_accepted, double *residuals);
 
 const char *lts_sur_last_error(const lts_sur *s);
 void lts_sur_destroy(lts_sur *s);

@@ -89,21 +89,24 @@ void build_graph(const DevMesh<T>& m, int N, int nFe, int32_t* adj, float* inv_d
 template <typename T>
 void features(const DevMesh<T>& m, const T* h, const T* u, int N, int cb1, int cb3, int cb4,
               float* raw, hipStream_t s);
-// tgt[0:nF] = h1 - h0, tgt[nF:nF+nFe] = u1 - u0 (FP32).
+// Training targets: the part of the step's increment beyond a forward-Euler
+// step, tgt[0:nF] = h1 - h0 - dt R0h, tgt[nF:nF+nFe] = u1 - u0 - dt R0u (FP32).
 template <typename T>
-void increments(const T* h0, const T* u0, const T* h1, const T* u1, int nF, int nFe, float* tgt,
-                hipStream_t s);
-// xh[i] = h[i] + sh * out_h[i] (i < nF), xu[e] = u[e] + su * out_u[e] (e < nFe).
+void increments(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h, const T* R0u,
+                double dt, int nF, int nFe, float* tgt, hipStream_t s);
+// xh[i] = h[i] + dt R0h[i] + scale[0] out_h[i] (i < nF),
+// xu[e] = u[e] + dt R0u[e] + scale[1] out_u[e] (e < nFe).
 template <typename T>
-void apply_increments(const T* h, const T* u, const float* out_h, const float* out_u,
-                      const float* scale, int nF, int nFe, T* xh, T* xu, hipStream_t s);
+void apply_increments(const T* h, const T* u, const T* R0h, const T* R0u, double dt,
+                      const float* out_h, const float* out_u, const float* scale, int nF, int nFe,
+                      T* xh, T* xu, hipStream_t s);
 // On i < nF (cells) and e < nFe (edges): mid = (a + b) / 2, then a = b.
 template <typename T>
 void midpoint_and_commit(T* ah, T* au, const T* bh, const T* bu, T* mh, T* mu, int nF, int nFe,
                          hipStream_t s);
 // Trapezoid residual sums on the fine region, FP64:
 //   out[0] = sum_i ((x1-x0)/dt - (R0+R1)/2)^2 over cells, out[1] = sum R0^2,
-//   out[2], out[3] the same over edges.
+//   out[2] = sum R1^2, out[3..5] the same over edges.
 template <typename T>
 void gate_sums(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h, const T* R0u,
                const T* R1h, const T* R1u, int nF, int nFe, double dt, double* part, double* out,

@@ -132,6 +132,23 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int nparts, int n
     out[i] = s;
 }
 
+// out[i] = sum_b part[b][i] with one block per output (many parts, few
+// outputs); fixed order within each block.
+__global__ void k_reduce_cols(const float* __restrict__ part, int nparts, int n,
+                              float* __restrict__ out) {
+    const int i = blockIdx.x;
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nparts; b += 256) s += part[(size_t)b * n + i];
+    __shared__ float sm[256];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sm[0];
+}
+
 // Wt[h][c][k] = W[64 h + k][c] for W [128 x 64]: the operand of dHC = dZ W^T
 // split into its two 64-column halves.
 __global__ void k_transpose_halves(const uint16_t* __restrict__ W, uint16_t* __restrict__ Wt) {
@@ -212,6 +229,21 @@ __device__ __forceinline__ float block_sum256(float v, float* sm) {
     return sm[0];
 }
 
+// sum_f row[f] w[f] over a 64-wide BF16 row (16-byte aligned), 8 at a time.
+__device__ __forceinline__ float dot_row(const uint16_t* __restrict__ row,
+                                         const float* __restrict__ w) {
+    float s = 0.f;
+    for (int q = 0; q < 8; ++q) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + 8 * q);
+        const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+        for (int j = 0; j < 4; ++j) {
+            s += __uint_as_float(x[j] << 16) * w[8 * q + 2 * j];
+            s += __uint_as_float(x[j] & 0xFFFF0000u) * w[8 * q + 2 * j + 1];
+        }
+    }
+    return s;
+}
+
 // One thread per fine cell (t < nF) or fine edge (nF <= t < nF + nFe).
 __global__ void k_heads(const uint16_t* __restrict__ H, int ldh, int nF, int nFe,
                         const int32_t* __restrict__ ec0, const int32_t* __restrict__ ec1,
@@ -224,8 +256,7 @@ __global__ void k_heads(const uint16_t* __restrict__ H, int ldh, int nF, int nFe
     const int t = blockIdx.x * 256 + threadIdx.x;
     float l = 0.f;
     if (t < nF) {
-        float s = bh[0];
-        for (int f = 0; f < 64; ++f) s += bf2f(H[(size_t)t * ldh + f]) * wh[f];
+        float s = bh[0] + dot_row(H + (size_t)t * ldh, wh);
         if (out_h) out_h[t] = s;
         if (th) {
             const float d = s - tsh * th[t];
@@ -234,10 +265,7 @@ __global__ void k_heads(const uint16_t* __restrict__ H, int ldh, int nF, int nFe
         }
     } else if (t < nF + nFe) {
         const int e = t - nF;
-        const int a = ec0[e], b = ec1[e];
-        float s = 0.f;
-        for (int f = 0; f < 64; ++f)
-            s += (bf2f(H[(size_t)b * ldh + f]) - bf2f(H[(size_t)a * ldh + f])) * wu[f];
+        const float s = dot_row(H + (size_t)ec1[e] * ldh, wu) - dot_row(H + (size_t)ec0[e] * ldh, wu);
         if (out_u) out_u[e] = s;
         if (tu) {
             const float d = s - tsu * tu[e];
@@ -251,22 +279,23 @@ __global__ void k_heads(const uint16_t* __restrict__ H, int ldh, int nF, int nFe
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// Four nodes per block, one thread per feature.
+// 64 nodes per block (4 at a time), one thread per feature.
 __global__ void k_heads_back(const uint16_t* __restrict__ H, int ldh, int N, int nF,
                              const int32_t* __restrict__ node_edges, int aw,
                              const float* __restrict__ wh, const float* __restrict__ wu,
                              const float* __restrict__ gh, const float* __restrict__ gu,
                              float* __restrict__ dH, float* __restrict__ part) {
     const int f = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + g;
     float pwh = 0.f, pwu = 0.f, pbh = 0.f;
-    if (i < N) {
+    for (int r = 0; r < 16; ++r) {
+        const int i = blockIdx.x * 64 + r * 4 + g;
+        if (i >= N) break;
         const float hv = bf2f(H[(size_t)i * ldh + f]);
         float d = 0.f;
         if (i < nF) {
             d += gh[i] * wh[f];
-            pwh = gh[i] * hv;
-            pbh = gh[i];
+            pwh += gh[i] * hv;
+            pbh += gh[i];
         }
         for (int s = 0; s < aw; ++s) {
             const int code = node_edges[(size_t)i * aw + s];
@@ -452,21 +481,26 @@ __global__ void k_features(DevMesh<T> m, const T* __restrict__ h, const T* __res
 
 template <typename T>
 __global__ void k_increments(const T* __restrict__ h0, const T* __restrict__ u0,
-                             const T* __restrict__ h1, const T* __restrict__ u1, int nF, int nFe,
-                             float* __restrict__ tgt) {
+                             const T* __restrict__ h1, const T* __restrict__ u1,
+                             const T* __restrict__ R0h, const T* __restrict__ R0u, T dt, int nF,
+                             int nFe, float* __restrict__ tgt) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < nF) tgt[t] = (float)(h1[t] - h0[t]);
-    else if (t < nF + nFe) tgt[t] = (float)(u1[t - nF] - u0[t - nF]);
+    if (t < nF) tgt[t] = (float)(h1[t] - h0[t] - dt * R0h[t]);
+    else if (t < nF + nFe) tgt[t] = (float)(u1[t - nF] - u0[t - nF] - dt * R0u[t - nF]);
 }
 
 template <typename T>
 __global__ void k_apply(const T* __restrict__ h, const T* __restrict__ u,
+                        const T* __restrict__ R0h, const T* __restrict__ R0u, T dt,
                         const float* __restrict__ out_h, const float* __restrict__ out_u,
                         const float* __restrict__ scale, int nF, int nFe, T* __restrict__ xh,
                         T* __restrict__ xu) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < nF) xh[t] = h[t] + (T)(scale[0] * out_h[t]);
-    else if (t < nF + nFe) xu[t - nF] = u[t - nF] + (T)(scale[1] * out_u[t - nF]);
+    if (t < nF) xh[t] = h[t] + dt * R0h[t] + (T)(scale[0] * out_h[t]);
+    else if (t < nF + nFe) {
+        const int e = t - nF;
+        xu[e] = u[e] + dt * R0u[e] + (T)(scale[1] * out_u[e]);
+    }
 }
 
 template <typename T>
@@ -493,37 +527,39 @@ __global__ void k_gate(const T* __restrict__ h0, const T* __restrict__ u0,
                        const T* __restrict__ R1h, const T* __restrict__ R1u, int nF, int nFe,
                        double dt, double* __restrict__ part) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (t < nF) {
         const double r =
             ((double)h1[t] - (double)h0[t]) / dt - 0.5 * ((double)R0h[t] + (double)R1h[t]);
         a[0] = r * r;
         a[1] = (double)R0h[t] * (double)R0h[t];
+        a[2] = (double)R1h[t] * (double)R1h[t];
     } else if (t < nF + nFe) {
         const int e = t - nF;
         const double r =
             ((double)u1[e] - (double)u0[e]) / dt - 0.5 * ((double)R0u[e] + (double)R1u[e]);
-        a[2] = r * r;
-        a[3] = (double)R0u[e] * (double)R0u[e];
+        a[3] = r * r;
+        a[4] = (double)R0u[e] * (double)R0u[e];
+        a[5] = (double)R1u[e] * (double)R1u[e];
     }
     __shared__ double sm[256];
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 6; ++k) {
         sm[threadIdx.x] = a[k];
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[blockIdx.x * 4 + k] = sm[0];
+        if (threadIdx.x == 0) part[blockIdx.x * 6 + k] = sm[0];
         __syncthreads();
     }
 }
 
 __global__ void k_gate_final(const double* __restrict__ part, int nparts, double* __restrict__ out) {
     const int k = threadIdx.x;
-    if (k >= 4) return;
+    if (k >= 6) return;
     double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[b * 4 + k];
+    for (int b = 0; b < nparts; ++b) s += part[b * 6 + k];
     out[k] = s;
 }
 
@@ -578,7 +614,7 @@ void colsum(const uint16_t* D, int N, int rows_per_block, float* part, float* ou
     const int np = colsum_parts(N, rows_per_block);
     if (np <= 0) return;
     hipLaunchKernelGGL(k_colsum, dim3(np), dim3(256), 0, s, D, N, rows_per_block, part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part, np, 64, out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(64), dim3(256), 0, s, part, np, 64, out);
 }
 
 int heads_parts(int nF, int nFe) { return (int)nblk((long)nF + nFe, 256); }
@@ -591,10 +627,10 @@ void heads(const uint16_t* H, int ldh, int nF, int nFe, const int32_t* ec0, cons
     if (n <= 0) return;
     hipLaunchKernelGGL(k_heads, dim3(n), dim3(256), 0, s, H, ldh, nF, nFe, ec0, ec1, wh, bh, wu,
                        th, tu, tsh, tsu, out_h, out_u, gh, gu, part);
-    if (part && loss) hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part, n, 1, loss);
+    if (part && loss) hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, s, part, n, 1, loss);
 }
 
-int heads_back_parts(int N) { return (int)nblk(N, 4); }
+int heads_back_parts(int N) { return (int)nblk(N, 64); }
 
 void heads_back(const uint16_t* H, int ldh, int N, int nF, const int32_t* node_edges, int aw,
                 const float* wh, const float* wu, const float* gh, const float* gu, float* dH,
@@ -603,7 +639,7 @@ void heads_back(const uint16_t* H, int ldh, int N, int nF, const int32_t* node_e
     if (n <= 0) return;
     hipLaunchKernelGGL(k_heads_back, dim3(n), dim3(256), 0, s, H, ldh, N, nF, node_edges, aw, wh,
                        wu, gh, gu, dH, part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part, n, 129, grads_head);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(129), dim3(256), 0, s, part, n, 129, grads_head);
 }
 
 void adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
@@ -650,19 +686,20 @@ void features(const DevMesh<T>& m, const T* h, const T* u, int N, int cb1, int c
 }
 
 template <typename T>
-void increments(const T* h0, const T* u0, const T* h1, const T* u1, int nF, int nFe, float* tgt,
-                hipStream_t s) {
+void increments(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h, const T* R0u,
+                double dt, int nF, int nFe, float* tgt, hipStream_t s) {
     if (nF + nFe > 0)
         hipLaunchKernelGGL((k_increments<T>), dim3(nblk((long)nF + nFe, 256)), dim3(256), 0, s, h0,
-                           u0, h1, u1, nF, nFe, tgt);
+                           u0, h1, u1, R0h, R0u, (T)dt, nF, nFe, tgt);
 }
 
 template <typename T>
-void apply_increments(const T* h, const T* u, const float* out_h, const float* out_u,
-                      const float* scale, int nF, int nFe, T* xh, T* xu, hipStream_t s) {
+void apply_increments(const T* h, const T* u, const T* R0h, const T* R0u, double dt,
+                      const float* out_h, const float* out_u, const float* scale, int nF, int nFe,
+                      T* xh, T* xu, hipStream_t s) {
     if (nF + nFe > 0)
         hipLaunchKernelGGL((k_apply<T>), dim3(nblk((long)nF + nFe, 256)), dim3(256), 0, s, h, u,
-                           out_h, out_u, scale, nF, nFe, xh, xu);
+                           R0h, R0u, (T)dt, out_h, out_u, scale, nF, nFe, xh, xu);
 }
 
 template <typename T>
@@ -689,10 +726,11 @@ void gate_sums(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h,
                                  int32_t*, int32_t*, hipStream_t);                               \
     template void features<T>(const DevMesh<T>&, const T*, const T*, int, int, int, int, float*, \
                               hipStream_t);                                                      \
-    template void increments<T>(const T*, const T*, const T*, const T*, int, int, float*,        \
-                                hipStream_t);                                                    \
-    template void apply_increments<T>(const T*, const T*, const float*, const float*,            \
-                                      const float*, int, int, T*, T*, hipStream_t);              \
+    template void increments<T>(const T*, const T*, const T*, const T*, const T*, const T*,      \
+                                double, int, int, float*, hipStream_t);                          \
+    template void apply_increments<T>(const T*, const T*, const T*, const T*, double,            \
+                                      const float*, const float*, const float*, int, int, T*,    \
+                                      T*, hipStream_t);                                          \
     template void midpoint_and_commit<T>(T*, T*, const T*, const T*, T*, T*, int, int,           \
                                          hipStream_t);                                           \
     template void gate_sums<T>(const T*, const T*, const T*, const T*, const T*, const T*,       \

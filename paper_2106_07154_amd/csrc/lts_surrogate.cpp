@@ -59,7 +59,7 @@ struct lts_sur {
     int loss_cap = 0;
     double* dpart = nullptr;
     double* gout = nullptr;
-    double* host4 = nullptr;  // pinned
+    double* host4 = nullptr;  // pinned, 6 gate sums
     int* flag = nullptr;
     // state-typed buffers (context precision)
     void *Sh = nullptr, *Su = nullptr, *R0h = nullptr, *R0u = nullptr, *R1h = nullptr,
@@ -68,6 +68,7 @@ struct lts_sur {
     float norm_host[16] = {0};
     bool has_norm = false;
     int adam_step = 0;
+    int skip = 0, backoff = 0;  // gate back-off state
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -209,6 +210,17 @@ void features_of_state(lts_sur* s, float* raw) {
     nn::features<T>(dm, (const T*)c->Ah, (const T*)c->Au, s->N, s->cb1, s->cb3, s->cb4, raw, s->s);
 }
 
+// R(x) on the fine cells and fine edges into (Rh, Ru).
+template <typename T>
+lts_status fine_rhs(lts_sur* s, const T* h, const T* u, T* Rh, T* Ru) {
+    lts_ctx* c = s->c;
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    Run<T> r{c, dm, s->s, false};
+    const Seg<T> none;
+    return r.pass(P_STEP3, h, u, Run<T>::upd(0, c->cb[3], Rh, nullptr, 0, nullptr, 0, 1.0), none,
+                  Run<T>::upd(0, c->eb[2], Ru, nullptr, 0, nullptr, 0, 1.0), none);
+}
+
 template <typename T>
 lts_status record_typed(lts_sur* s, double dt, int M, int n) {
     lts_ctx* c = s->c;
@@ -216,10 +228,13 @@ lts_status record_typed(lts_sur* s, double dt, int M, int n) {
         features_of_state<T>(s, s->raw_s + (size_t)s->S * s->N * nn::kFeat);
         SCHK(s, hipMemcpyAsync(s->Sh, c->Ah, c->nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
         SCHK(s, hipMemcpyAsync(s->Su, c->Au, c->nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
-        lts_status st = lts_step(c, dt, M, 1);
+        lts_status st = fine_rhs<T>(s, (const T*)c->Ah, (const T*)c->Au, (T*)s->R0h, (T*)s->R0u);
+        if (st) return sfail(s, st, std::string("right-hand side: ") + lts_last_error(c));
+        st = lts_step(c, dt, M, 1);
         if (st) return sfail(s, st, std::string("LTS3 step: ") + lts_last_error(c));
-        nn::increments<T>((const T*)s->Sh, (const T*)s->Su, (const T*)c->Ah, (const T*)c->Au, s->nF,
-                          s->nFe, s->tgt_s + (size_t)s->S * (s->nF + s->nFe), s->s);
+        nn::increments<T>((const T*)s->Sh, (const T*)s->Su, (const T*)c->Ah, (const T*)c->Au,
+                          (const T*)s->R0h, (const T*)s->R0u, dt, s->nF, s->nFe,
+                          s->tgt_s + (size_t)s->S * (s->nF + s->nFe), s->s);
         SCHK(s, hipGetLastError());
         ++s->S;
     }
@@ -244,14 +259,13 @@ lts_status enqueue_sur_step(lts_sur* s, double dt) {
     SCHK(s, hipMemcpyAsync(s->Sh, Ah, nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     SCHK(s, hipMemcpyAsync(s->Su, Au, nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     // R(x_n) on F
-    if ((st = r.pass(P_STEP3, Ah, Au, Run<T>::upd(0, cb[3], R0h, nullptr, 0, nullptr, 0, 1.0), none,
-                     Run<T>::upd(0, eb[2], R0u, nullptr, 0, nullptr, 0, 1.0), none)))
-        return st;
-    // network prediction of F at t + dt into B
+    if ((st = fine_rhs<T>(s, Ah, Au, R0h, R0u))) return st;
+    // F at t + dt into B: a forward-Euler step plus the network's correction
     features_of_state<T>(s, s->raw);
     nn::norm_features(s->raw, s->N, s->norm, s->norm + 5, s->X, s->s);
     forward(s, nullptr, nullptr, nullptr);
-    nn::apply_increments<T>(Ah, Au, s->out_h, s->out_u, s->norm + 12, s->nF, s->nFe, Bh, Bu, s->s);
+    nn::apply_increments<T>(Ah, Au, R0h, R0u, dt, s->out_h, s->out_u, s->norm + 12, s->nF, s->nFe,
+                            Bh, Bu, s->s);
     // SSPRK3 on I u C with F read at t, t + dt, t + dt/2
     if ((st = r.pass(P_STEP2, Ah, Au, Run<T>::upd(cb[3], nC, Bh, nullptr, 0, Ah, 1, dt), none,
                      Run<T>::upd(eb[2], nE, Bu, nullptr, 0, Au, 1, dt), none)))
@@ -266,9 +280,7 @@ lts_status enqueue_sur_step(lts_sur* s, double dt) {
                      none)))
         return st;
     // R(x_pred) on F (I1 now at t + dt) and the residual sums
-    if ((st = r.pass(P_STEP3, Ah, Au, Run<T>::upd(0, cb[3], R1h, nullptr, 0, nullptr, 0, 1.0), none,
-                     Run<T>::upd(0, eb[2], R1u, nullptr, 0, nullptr, 0, 1.0), none)))
-        return st;
+    if ((st = fine_rhs<T>(s, Ah, Au, R1h, R1u))) return st;
     nn::gate_sums<T>((const T*)s->Sh, (const T*)s->Su, Ah, Au, R0h, R0u, R1h, R1u, s->nF, s->nFe,
                      dt, s->dpart, s->gout, s->s);
     return LTS_OK;
@@ -303,29 +315,42 @@ lts_status capture_step(lts_sur* s, double dt) {
 }
 
 template <typename T>
-lts_status sur_step_typed(lts_sur* s, double dt, int M, int n, double tau, int* n_acc,
-                          double* resid) {
+lts_status sur_step_typed(lts_sur* s, double dt, int M, int n, double tau, int max_backoff,
+                          int* n_acc, double* resid) {
     lts_ctx* c = s->c;
     lts_status st;
     if ((st = capture_step<T>(s, dt))) return st;
     int acc = 0;
     for (int k = 0; k < n; ++k) {
+        if (s->skip > 0) {  // backing off after a rejection: plain LTS3
+            --s->skip;
+            if (resid) resid[k] = -1.0;
+            if ((st = lts_step(c, dt, M, 1)))
+                return sfail(s, st, std::string("LTS3 step: ") + lts_last_error(c));
+            continue;
+        }
         SCHK(s, hipGraphLaunch(s->gexec, s->s));
-        SCHK(s, hipMemcpyAsync(s->host4, s->gout, 4 * sizeof(double), hipMemcpyDeviceToHost, s->s));
+        SCHK(s, hipMemcpyAsync(s->host4, s->gout, 6 * sizeof(double), hipMemcpyDeviceToHost, s->s));
         SCHK(s, hipStreamSynchronize(s->s));
         const double* o = s->host4;
-        auto ratio = [](double num, double den) {
-            if (den > 0.0) return std::sqrt(num / den);
+        // ||defect|| / ((||R(x_n)|| + ||R(x_pred)||) / 2), per field
+        auto ratio = [](double num, double d0, double d1) {
+            const double den = 0.5 * (std::sqrt(d0) + std::sqrt(d1));
+            if (den > 0.0) return std::sqrt(num) / den;
             return num > 0.0 || std::isnan(num) ? std::numeric_limits<double>::infinity() : 0.0;
         };
-        double r = std::max(ratio(o[0], o[1]), ratio(o[2], o[3]));
-        if (std::isnan(o[0]) || std::isnan(o[2])) r = std::numeric_limits<double>::quiet_NaN();
+        double r = std::max(ratio(o[0], o[1], o[2]), ratio(o[3], o[4], o[5]));
+        for (int q = 0; q < 6; ++q)
+            if (std::isnan(o[q])) r = std::numeric_limits<double>::quiet_NaN();
         if (resid) resid[k] = r;
         if (std::isfinite(r) && r < tau) {
             ++acc;
             c->t += dt;
             c->steps += 1;
+            s->backoff = 0;
         } else {
+            s->backoff = std::min(max_backoff, s->backoff ? 2 * s->backoff : 1);
+            s->skip = s->backoff;
             SCHK(s, hipMemcpyAsync(c->Ah, s->Sh, c->nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
             SCHK(s, hipMemcpyAsync(c->Au, s->Su, c->nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
             // the context stream runs the fallback; order it after the copies
@@ -408,7 +433,7 @@ lts_status lts_sur_create(lts_sur** out, lts_ctx* c, int n_layers, int hidden, u
         (st = salloc(s, &s->out_h, s->nF * 4)) || (st = salloc(s, &s->out_u, s->nFe * 4)) ||
         (st = salloc(s, &s->gh, s->nF * 4)) || (st = salloc(s, &s->gu, s->nFe * 4)) ||
         (st = salloc(s, &s->part, part * 4)) || (st = salloc(s, &s->norm, 16 * 4)) ||
-        (st = salloc(s, &s->dpart, 256 * 12 * 8)) || (st = salloc(s, &s->gout, 4 * 8)) ||
+        (st = salloc(s, &s->dpart, 256 * 12 * 8)) || (st = salloc(s, &s->gout, 6 * 8)) ||
         (st = salloc(s, &s->flag, 64)))
         return fail_out(st);
     for (int l = 0; l < kLayers; ++l) {
@@ -417,12 +442,12 @@ lts_status lts_sur_create(lts_sur** out, lts_ctx* c, int n_layers, int hidden, u
     }
     // the gate sums need one partial per 256 fine elements
     const size_t gparts = (nT + 255) / 256;
-    if (gparts * 4 > 256 * 12) {
+    if (gparts * 6 > 256 * 12) {
         double* gp = nullptr;
-        if ((st = salloc(s, &gp, gparts * 4 * 8))) return fail_out(st);
+        if ((st = salloc(s, &gp, gparts * 6 * 8))) return fail_out(st);
         s->dpart = gp;
     }
-    if (hipHostMalloc((void**)&s->host4, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&s->host4, 6 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         s->err = "hipHostMalloc failed";
         return fail_out(LTS_ENOMEM);
     }
@@ -597,14 +622,17 @@ lts_status lts_sur_predict(lts_sur* s, float* oh, float* ou) {
     return LTS_OK;
 }
 
-lts_status lts_sur_step(lts_sur* s, double dt, int M, int n, double tau, int* n_acc,
-                        double* resid) {
+lts_status lts_sur_step(lts_sur* s, double dt, int M, int n, double tau, int max_backoff,
+                        int* n_acc, double* resid) {
     lts_status st = check(s);
     if (st) return st;
     if (!(dt > 0) || M < 1 || n < 0) return sfail(s, LTS_EINVAL, "need dt > 0, M >= 1, n >= 0");
     if (!s->has_norm) return sfail(s, LTS_EINVAL, "normalisation not set");
-    return s->c->prec == LTS_FP64 ? sur_step_typed<double>(s, dt, M, n, tau, n_acc, resid)
-                                  : sur_step_typed<float>(s, dt, M, n, tau, n_acc, resid);
+    if (max_backoff < 0) return sfail(s, LTS_EINVAL, "need max_backoff >= 0");
+    if (max_backoff == 0) s->skip = s->backoff = 0;
+    return s->c->prec == LTS_FP64
+               ? sur_step_typed<double>(s, dt, M, n, tau, max_backoff, n_acc, resid)
+               : sur_step_typed<float>(s, dt, M, n, tau, max_backoff, n_acc, resid);
 }
 
 const char* lts_sur_last_error(const lts_sur* s) { return s ? s->err.c_str() : "null surrogate"; }

@@ -157,3 +157,20 @@ def ensemble_members(n_members=64, iters=10, workers=None, seed=ENS_SEED):
         for f in cf.as_completed(futs):
             out[futs[f]] = f.result()
     return out
+
+
+# ---------------------------------------------------------------------------
+# Training trajectories of the fine-region surrogate (on the vr_planar mesh)
+
+SUR_SEED = 8000
+
+
+def surrogate_initial_state(mesh, i, H=500.0, seed=SUR_SEED):
+    """Initial state of trajectory i: a Gaussian bump of 5(1 + 0.2 z) m,
+    sigma 40(1 + 0.1 z) km, centre jittered by up to 50 km around the
+    domain centre, at rest over H = 500 m."""
+    rng = np.random.default_rng(seed + i)
+    z = rng.standard_normal(2)
+    L = vp.VR_DOMAIN
+    cx, cy = L / 2 + rng.uniform(-5.0e4, 5.0e4, 2)
+    return gaussian_bump_state(mesh, H, 5.0 * (1 + 0.2 * z[0]), 4.0e4 * (1 + 0.1 * z[1]), cx, cy)

@@ -128,7 +128,7 @@ def load_library(path: str = LIB_PATH):
         "lts_sur_grad": ([P, ci, P, P], ci),
         "lts_sur_features": ([P, P], ci),
         "lts_sur_predict": ([P, P, P], ci),
-        "lts_sur_step": ([P, cd, ci, ci, cd, P, P], ci),
+        "lts_sur_step": ([P, cd, ci, ci, cd, ci, P, P], ci),
         "lts_sur_last_error": ([P], ctypes.c_char_p),
         "lts_sur_destroy": ([P], None),
         "lts_nn_gemm_bf16": ([ci, P, ci, ci, P, P, P], ci),
@@ -514,11 +514,11 @@ class Surrogate:
         self._check(self._lib.lts_sur_predict(self._h, _ptr(oh), _ptr(ou)))
         return oh, ou
 
-    def step(self, dt: float, M: int, n_steps: int = 1, tau: float = 0.0):
+    def step(self, dt: float, M: int, n_steps: int = 1, tau: float = 0.0, max_backoff: int = 0):
         acc = np.zeros(1, np.int32)
         res = np.empty(max(n_steps, 1))
         self._check(self._lib.lts_sur_step(self._h, float(dt), int(M), int(n_steps), float(tau),
-                                           _ptr(acc), _ptr(res)))
+                                           int(max_backoff), _ptr(acc), _ptr(res)))
         return int(acc[0]), res[:n_steps]
 
 

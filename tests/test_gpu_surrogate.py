@@ -168,8 +168,9 @@ def test_gradient_parity(lloyd_setup):
     ctx.init_state(S["h"], S["u"])
     sur.record(dt, 4, 1)
     h1, u1 = o.lts(S["h"], S["u"], dt, 4, S["reg"], n=1)
-    th = (h1 - S["h"])[G.nodes[:G.fine]]
-    tu = (u1 - S["u"])[G.edges]
+    R0h, R0u = o.rhs(S["h"], S["u"])
+    th = (h1 - S["h"] - dt * R0h)[G.nodes[:G.fine]]
+    tu = (u1 - S["u"] - dt * R0u)[G.edges]
     ref_raw = mpnn.raw_features(m, o, S["reg"], S["h"], S["u"], G.nodes)
     norm = _norm_from(ref_raw, th, tu)
     p = _test_params(12)
@@ -204,9 +205,11 @@ def _ctx(w, prec="fp64"):
 
 
 def test_zero_network_step_matches_oracle(igw):
-    """All-zero parameters predict no change on F: the surrogate step is then
-    SSPRK3 on I u C with F frozen, and r = ||(R(x_n) + R(x_new))/2|| /
-    ||R(x_n)|| on F; both follow from the oracle's right-hand side."""
+    """All-zero parameters leave the forward-Euler prediction x_n + dt R(x_n)
+    on F: the surrogate step is then SSPRK3 on I u C reading F at x_n, the
+    prediction and their mean, and r = ||(R(x_n) - R(x_new))/2|| /
+    ((||R(x_n)|| + ||R(x_new)||)/2) on F; all of it follows from the oracle's
+    right-hand side."""
     w = igw
     say("zero-network surrogate step", w.name)
     c = _ctx(w)
@@ -220,25 +223,30 @@ def test_zero_network_step_matches_oracle(igw):
     reg = o.regions(w.fine_mask, w.n_if1, w.n_if2)
     fc, fe = reg.cell == F, reg.edge == F
     x0h, x0u, dt = w.h0, w.u0, w.dt_coarse
+    R0 = o.rhs(x0h, x0u)
+    ph, pu = x0h + dt * R0[0], x0u + dt * R0[1]      # forward-Euler prediction on F
 
-    def stage(xh, xu, baseh, baseu, a, b):
+    def stage(xh, xu, baseh, baseu, a, b, fh, fu):
         dh, du = o.rhs(xh, xu)
         nh = a * baseh + b * (xh + dt * dh)
         nu = a * baseu + b * (xu + dt * du)
-        nh[fc], nu[fe] = x0h[fc], x0u[fe]
+        nh[fc], nu[fe] = fh[fc], fu[fe]
         return nh, nu
 
-    y1 = stage(x0h, x0u, x0h, x0u, 0.0, 1.0)
-    y2 = stage(*y1, x0h, x0u, 0.75, 0.25)
-    y3 = stage(*y2, x0h, x0u, 1.0 / 3.0, 2.0 / 3.0)
-    assert np.array_equal(h[fc], x0h[fc]) and np.array_equal(u[fe], x0u[fe])
+    y1 = stage(x0h, x0u, x0h, x0u, 0.0, 1.0, ph, pu)
+    y2 = stage(*y1, x0h, x0u, 0.75, 0.25, 0.5 * (x0h + ph), 0.5 * (x0u + pu))
+    y3 = stage(*y2, x0h, x0u, 1.0 / 3.0, 2.0 / 3.0, ph, pu)
+    # the u tendency is a difference of g(h + b) ~ gH terms: its FP64 floor
+    # is ~1e-12 relative, held at 1e-11 as in the solver's own parity tests
+    assert rel_l2(h[fc], ph[fc]) < 1e-14 and rel_l2(u[fe] - x0u[fe], pu[fe] - x0u[fe]) < 1e-11
     assert rel_l2(h, y3[0]) < 1e-12 and rel_l2(u - x0u, y3[1] - x0u) < 1e-10
-    R0 = o.rhs(x0h, x0u)
     R1 = o.rhs(*y3)
-    rh = np.linalg.norm(0.5 * (R0[0] + R1[0])[fc]) / np.linalg.norm(R0[0][fc])
-    ru = np.linalg.norm(0.5 * (R0[1] + R1[1])[fe]) / np.linalg.norm(R0[1][fe])
-    say("residual", res[0], max(rh, ru))
-    assert abs(res[0] - max(rh, ru)) <= 1e-10 * max(rh, ru)
+
+    def r(a, b, m):
+        return np.linalg.norm(0.5 * (a - b)[m]) / (0.5 * (np.linalg.norm(a[m]) + np.linalg.norm(b[m])))
+    want = max(r(R0[0], R1[0], fc), r(R0[1], R1[1], fe))
+    say("residual", res[0], want)
+    assert abs(res[0] - want) <= 1e-9 * want
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -284,3 +292,20 @@ def test_training_reduces_loss_and_gate_accepts(igw):
     assert acc == 4 and np.all(np.isfinite(res))
     d = c.diagnostics()
     assert d.n_nonfinite == 0 and d.steps == 44
+
+
+def test_gate_backoff_schedule(igw):
+    w = igw
+    say("surrogate back-off")
+    a, b = _ctx(w), _ctx(w)
+    sur = lts.Surrogate(a, seed=4)
+    sur.set_norm(np.array([0] * 5 + [1] * 9 + [0, 0], np.float32))
+    acc, res = sur.step(w.dt_coarse, w.M, 8, tau=0.0, max_backoff=4)
+    assert acc == 0
+    assert [k for k in range(8) if res[k] >= 0] == [0, 2, 5]     # skips of 1, 2, 4 steps
+    assert np.all(res[[1, 3, 4, 6, 7]] == -1.0)
+    b.step(w.dt_coarse, w.M, 8)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    assert a.diagnostics().steps == 8

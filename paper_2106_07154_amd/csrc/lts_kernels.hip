@@ -76,9 +76,11 @@ __device__ __forceinline__ void epilogue(int j, T G, const Seg<T>& s0, const Seg
     else if (s1.mode && j >= s1.lo && j < s1.hi) apply_seg(j, G, s1, flag);
 }
 
+// Potential vorticity at vertex v: (f_v A_v + circulation) / (A_v h_v) with
+// h_v the kite-weighted thickness.
 template <typename T>
-__device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __restrict__ h,
-                                            const T* __restrict__ u, T* __restrict__ q, int v) {
+__device__ __forceinline__ T vertex_q(const DevMesh<T>& m, const T* __restrict__ h,
+                                      const T* __restrict__ u, int v) {
     const int nV = m.nV;
     T circ = 0, hv = 0;
 #pragma unroll
@@ -88,7 +90,13 @@ __device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __rest
         circ += m.tdc[o] * u[m.eov[o]];
         hv += m.kite[o] * (m.href ? m.href[c] + h[c] : h[c]);
     }
-    q[v] = (m.fA[v] + circ) / hv;
+    return (m.fA[v] + circ) / hv;
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __restrict__ h,
+                                            const T* __restrict__ u, T* __restrict__ q, int v) {
+    q[v] = vertex_q(m, h, u, v);
 }
 
 template <typename T>
@@ -148,7 +156,10 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     const T hi = href ? href[i] + h[i] : h[i];
     const T hn = href ? href[nb] + h[nb] : h[nb];
     const T ue = u[e];
-    const T qv = q[v];
+    // q == nullptr: no vertex pass ran; each lane evaluates the PV of its own
+    // vertex (every vertex is then evaluated by each of its cells, with the
+    // same arithmetic as the vertex kernel)
+    const T qv = q ? q[v] : vertex_q(m, h, u, v);
     const T Ga = nl * (T(0.5) * (hi + hn) * ue);
     const T K = gsum<T, G>(kc * ue * ue);
     const T Sinc = gscan<T, G>(kf, lane);

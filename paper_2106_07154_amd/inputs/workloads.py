@@ -174,3 +174,88 @@ def surrogate_initial_state(mesh, i, H=500.0, seed=SUR_SEED):
     L = vp.VR_DOMAIN
     cx, cy = L / 2 + rng.uniform(-5.0e4, 5.0e4, 2)
     return gaussian_bump_state(mesh, H, 5.0 * (1 + 0.2 * z[0]), 4.0e4 * (1 + 0.1 * z[1]), cx, cy)
+
+
+# ---------------------------------------------------------------------------
+# The variable-resolution sphere (1.6M cells)
+
+SPH_SEED = 2106071541
+SPH_N = 1_600_000
+SPH_ITERS = 30
+
+
+def _sphere_cache_path(n, seed, iters):
+    return os.path.join(DATA, f"sphere{n}_s{seed}_i{iters}_u32.npy")
+
+
+def sphere_points_cached(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, progress=None):
+    from . import voronoi_sphere as vs
+    path = _sphere_cache_path(n, seed, iters)
+    if os.path.exists(path):
+        return vs.dequantize_lonlat(np.load(path, allow_pickle=False))
+    p = vs.morton_sort_sphere(vs.cap_points(n, seed, iters, progress))
+    return vs.dequantize_lonlat(vs.quantize_lonlat(p))
+
+
+def _plane_wave_field(x, kmax, n_waves, rng):
+    """Random-phase superposition of n_waves plane waves exp(i R k.x) with
+    random directions and |k| R uniform in [1, kmax], restricted to the unit
+    vectors x: a smooth random field whose spectrum ends near degree kmax.
+    Returned with zero mean and unit RMS over the points."""
+    d = rng.standard_normal((n_waves, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    k = rng.uniform(1.0, kmax, n_waves)
+    ph = rng.uniform(0.0, 2 * math.pi, n_waves)
+    amp = 1.0 / k
+    f = np.zeros(len(x))
+    for j in range(n_waves):
+        f += amp[j] * np.cos(k[j] * (x @ d[j]) + ph[j])
+    f -= f.mean()
+    return f / math.sqrt(np.mean(f * f))
+
+
+def sphere_state(m, u0=20.0, depth=5000.0, noise_rms=10.0, topo_rms=500.0, seed=SPH_SEED,
+                 g=9.81):
+    """Zonal flow u = u0 cos(lat) in gradient-wind balance (the surface height
+    of the steady zonal-flow solution on the rotating sphere), random
+    topography (plane-wave spectrum up to degree 16, 500 m RMS), random height
+    noise (up to degree 32, 10 m RMS), mean depth 5000 m.  Sets m.bottom;
+    returns (h, u)."""
+    from . import voronoi_sphere as vs
+    R, Om = vs.EARTH_RADIUS, vs.OMEGA
+    rng = np.random.default_rng(seed + 3)
+    xc = np.stack([m.xCell, m.yCell, m.zCell], 1) / R
+    lat = np.arcsin(np.clip(xc[:, 2], -1, 1))
+    b = topo_rms * _plane_wave_field(xc, 16.0, 256, np.random.default_rng(seed + 4))
+    m.bottom = b
+    surf = -(R * Om * u0 + 0.5 * u0 * u0) * np.sin(lat) ** 2 / g
+    h = surf - b + noise_rms * _plane_wave_field(xc, 32.0, 256, rng)
+    h += depth - np.sum(m.areaCell * h) / np.sum(m.areaCell)
+    xe = np.stack([m.xEdge, m.yEdge, m.zEdge], 1) / R
+    late = np.arcsin(np.clip(xe[:, 2], -1, 1))
+    lone = np.arctan2(xe[:, 1], xe[:, 0])
+    east = np.stack([-np.sin(lone), np.cos(lone), np.zeros_like(lone)], 1)
+    u = u0 * np.cos(late) * np.einsum("ij,ij->i", east, m.normalEdge)
+    return h, u
+
+
+def sphere_cap(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, M=4, progress=None) -> Workload:
+    """The variable-resolution sphere: n points Lloyd-relaxed `iters` times
+    under rho ~ s^-4 with s 1 inside a 20-degree cap at (3 pi/2, pi/6) and 4
+    outside (3-degree tanh transition), radius 6371 km, f = 2 Omega sin(lat);
+    balanced zonal jet over random topography; fine region: target spacing
+    below 0.9 of the outer one; interface 2 + 2 rings; the fine step is 0.3 of
+    the crossing time of the smallest cell at the fastest gravity-wave speed
+    plus the jet speed."""
+    from . import voronoi_sphere as vs
+    P = sphere_points_cached(n, seed, iters, progress)
+    m = vs.sphere_voronoi_mesh(P, name=f"sphere{n}")
+    xc = np.stack([m.xCell, m.yCell, m.zCell], 1) / vs.EARTH_RADIUS
+    fm = (vs.cap_spacing_shape(xc) < 0.9 * vs.CAP_RATIO).astype(np.uint8)
+    h0, u0 = sphere_state(m, seed=seed)
+    spacing = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
+    c = math.sqrt(9.81 * float((h0 + m.bottom).max())) + 20.0
+    dt_fine = 0.3 * spacing.min() / c
+    return Workload(f"sphere-{n // 1000}k", m, fm, h0, u0, dt_fine * M, M,
+                    extra=dict(dt_fine=dt_fine, spacing_min=float(spacing.min()),
+                               spacing_max=float(spacing.max())))

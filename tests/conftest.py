@@ -57,3 +57,14 @@ def lloyd_mesh():
     for _ in range(15):
         p = lloyd_step(p, L, L, lambda x, y: sp(x, y) ** -4.0)
     return periodic_voronoi_mesh(p, L, L, f0=1.0e-4, name="lloyd600")
+
+
+@pytest.fixture(scope="session")
+def sphere_mesh():
+    """Small variable-resolution spherical Voronoi mesh (3,000 cells, 20 Lloyd
+    iterations, fine cap ratio 4), random topography."""
+    from paper_2106_07154_amd.inputs import voronoi_sphere as vs
+    P = vs.cap_points(3000, 5, 20)
+    m = vs.sphere_voronoi_mesh(vs.morton_sort_sphere(P), name="sphere3000")
+    m.bottom = 100.0 * np.random.default_rng(6).standard_normal(m.nCells)
+    return m

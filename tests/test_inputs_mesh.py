@@ -74,3 +74,30 @@ def test_voronoi_builder_reproduces_hex():
     np.testing.assert_allclose(np.sort(m.dvEdge), np.sort(ref.dvEdge), rtol=1e-6)
     np.testing.assert_allclose(np.sort(m.areaCell), np.sort(ref.areaCell), rtol=1e-6)
     np.testing.assert_allclose(m.kiteAreasOnVertex, ref.kiteAreasOnVertex[0, 0], rtol=1e-6)
+
+
+def test_sphere_invariants(sphere_mesh):
+    """Spherical Voronoi: Euler characteristic 2, kites tile the sphere and
+    the dual triangles, normals point from c0 to c1 and tangents k x n from
+    v0 to v1 (k outward), variable resolution as designed."""
+    import math
+    from paper_2106_07154_amd.inputs import voronoi_sphere as vs
+    m = sphere_mesh
+    m.check()
+    assert m.nVertices - m.nEdges + m.nCells == 2
+    S = 4 * math.pi * vs.EARTH_RADIUS ** 2
+    assert abs(m.areaCell.sum() / S - 1) < 1e-13
+    assert abs(m.areaTriangle.sum() / S - 1) < 1e-13
+    xc = np.stack([m.xCell, m.yCell, m.zCell], 1)
+    xv = np.stack([m.xVertex, m.yVertex, m.zVertex], 1)
+    k = np.stack([m.xEdge, m.yEdge, m.zEdge], 1)
+    k /= np.linalg.norm(k, axis=1)[:, None]
+    dc = xc[m.cellsOnEdge[:, 1]] - xc[m.cellsOnEdge[:, 0]]
+    dv = xv[m.verticesOnEdge[:, 1]] - xv[m.verticesOnEdge[:, 0]]
+    assert (np.einsum("ij,ij->i", m.normalEdge, dc) > 0).all()
+    assert (np.einsum("ij,ij->i", np.cross(k, m.normalEdge), dv) > 0).all()
+    np.testing.assert_allclose(np.linalg.norm(m.normalEdge, axis=1), 1.0, rtol=1e-14)
+    assert (np.abs(np.einsum("ij,ij->i", m.normalEdge, k)) < 1e-12).all()
+    s = vs.cap_spacing_shape(xc / vs.EARTH_RADIUS)
+    a_in, a_out = m.areaCell[s < 1.2].mean(), m.areaCell[s > 3.8].mean()
+    assert 8.0 < a_out / a_in < 24.0

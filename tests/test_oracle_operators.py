@@ -38,7 +38,7 @@ def test_weights_regular_hex_pattern(hex16):
                                    sorted([1 / 3, 1 / 6, 0.0, 1 / 6, 1 / 3] * 2), atol=1e-15)
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
 def test_weights_antisymmetric(meshname, request):
     """w_{e,e'} = -w_{e',e}: the property behind energy conservation."""
     m = request.getfixturevalue(meshname)
@@ -115,7 +115,7 @@ def test_vorticity_of_linear_field(meshname, request):
 
 
 # ---------------------------------------------------------------- invariants
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
 def test_lake_at_rest(meshname, request):
     m = request.getfixturevalue(meshname).copy()
     rng = np.random.default_rng(4)
@@ -126,7 +126,7 @@ def test_lake_at_rest(meshname, request):
     assert np.abs(du).max() < 1e-12 * G * 1000.0 / m.dcEdge.min()
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
 def test_energy_and_mass_identities(meshname, request):
     """sum_i A_i (K_i + g(h_i+b_i)) H_i + sum_e l_e d_e h_e u_e U_e = 0 and
     sum_i A_i H_i = 0 for any state: the semi-discrete system conserves energy
@@ -234,7 +234,7 @@ def test_igw_second_order_in_space_and_polarisation():
     assert errs[-1][0] < 0.01 and errs[-1][1] < 0.01
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "sphere_mesh"])
 def test_diagnostic_energy_is_conserved_by_rhs(meshname, request):
     """The diagnostic total energy sum_i A_i (h_i K_i + g(h_i^2/2 + h_i b_i)) is
     the invariant of the semi-discrete system: its derivative along R(x),
@@ -256,3 +256,24 @@ def test_diagnostic_energy_is_conserved_by_rhs(meshname, request):
     mp, _ = o.diagnostics(h + eps * dh, u)
     m0, _ = o.diagnostics(h, u)
     assert abs(mp - m0) < 1e-12 * m0
+
+
+def test_sphere_balanced_zonal_flow_is_nearly_steady(sphere_mesh):
+    """The zonal flow u0 cos(lat) with the gradient-wind surface height is a
+    steady solution of the equations on the rotating sphere; the discrete
+    tendencies are truncation-sized, far below the Coriolis and pressure
+    terms they balance (a wrong Coriolis sign doubles them instead)."""
+    from paper_2106_07154_amd.inputs import voronoi_sphere as vs
+    from paper_2106_07154_amd.inputs.workloads import sphere_state
+    m = sphere_mesh.copy()
+    h, u = sphere_state(m, noise_rms=0.0, topo_rms=0.0)
+    dh, du = Oracle(m).rhs(h, u)
+    fu = 2 * vs.OMEGA * 20.0
+    rms = lambda a: float(np.sqrt(np.mean(a * a)))
+    assert rms(du) < 0.05 * fu and np.abs(du).max() < 0.3 * fu
+    # thickness tendency against the flux-divergence scale H u0 / dc
+    assert rms(dh) < 0.05 * 5000.0 * 20.0 / 3.0e5
+    # the same state with the sign of f reversed is far from steady
+    m.fVertex = -m.fVertex
+    _, du_bad = Oracle(m).rhs(h, u)
+    assert rms(du_bad) > 10 * rms(du)

@@ -248,6 +248,27 @@ def cap_points(n, seed, iters, progress=None):
     return p
 
 
+def max_cell_degree(P):
+    """Largest number of Voronoi edges of a cell (Delaunay degree)."""
+    from scipy.spatial import ConvexHull
+    return int(np.bincount(ConvexHull(P).simplices.ravel(), minlength=len(P)).max())
+
+
+def relax_to_degree(P, max_degree=8, max_extra=20, progress=None):
+    """Further Lloyd iterations until no cell has more than max_degree edges;
+    returns (points, iterations done)."""
+    dens = lambda x: cap_spacing_shape(x) ** -4.0
+    done = 0
+    while max_cell_degree(P) > max_degree:
+        if done >= max_extra:
+            raise ValueError("cells with too many edges remain")
+        P = lloyd_step_sphere(P, dens)
+        done += 1
+        if progress:
+            progress(done)
+    return P, done
+
+
 def morton_sort_sphere(P):
     """Order unit vectors along a 3-D Morton curve (locality of cell ids)."""
     q = np.clip(((P + 1.0) * 0.5 * 1023.0).astype(np.int64), 0, 1023)

@@ -185,7 +185,27 @@ SPH_ITERS = 30
 
 
 def _sphere_cache_path(n, seed, iters):
-    return os.path.join(DATA, f"sphere{n}_s{seed}_i{iters}_u32.npy")
+    return os.path.join(DATA, f"sphere{n}_s{seed}_i{iters}_deg8_u32.npy")
+
+
+def sphere_points(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, progress=None):
+    """The relaxation recipe: `iters` Lloyd iterations from the seeded sample,
+    Morton order, uint32 fixed point, then further iterations (each followed
+    by the same ordering and fixed point) until no cell has more than 8
+    edges.  Returns the fixed-point (longitude, latitude) array."""
+    from . import voronoi_sphere as vs
+    q = vs.quantize_lonlat(vs.morton_sort_sphere(vs.cap_points(n, seed, iters, progress)))
+    dens = lambda x: vs.cap_spacing_shape(x) ** -4.0
+    extra = 0
+    while vs.max_cell_degree(vs.dequantize_lonlat(q)) > 8:
+        if extra >= 20:
+            raise ValueError("cells with more than 8 edges remain")
+        p = vs.lloyd_step_sphere(vs.dequantize_lonlat(q), dens)
+        q = vs.quantize_lonlat(vs.morton_sort_sphere(p))
+        extra += 1
+        if progress:
+            progress(iters + extra - 1)
+    return q
 
 
 def sphere_points_cached(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, progress=None):
@@ -193,8 +213,7 @@ def sphere_points_cached(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, progress=None)
     path = _sphere_cache_path(n, seed, iters)
     if os.path.exists(path):
         return vs.dequantize_lonlat(np.load(path, allow_pickle=False))
-    p = vs.morton_sort_sphere(vs.cap_points(n, seed, iters, progress))
-    return vs.dequantize_lonlat(vs.quantize_lonlat(p))
+    return vs.dequantize_lonlat(sphere_points(n, seed, iters, progress))
 
 
 def _plane_wave_field(x, kmax, n_waves, rng):

@@ -118,22 +118,59 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __rest
 // so for any slot quantity X
 //   sum_{a != b} (R_ab - 1/2) X_a = (S_b - 1/2)(sum X - X_b)
 //                                   - (sum S X - S_b X_b) + S_n sum_{a > b} X_a,
-// and the PV sum is (1/2) q~_b P_b(G) + (1/2) P_b(G q~).  Group sums and scans
-// use cross-lane shuffles within the G lanes of a cell.
+// and the PV sum is (1/2) q~_b P_b(G) + (1/2) P_b(G q~).  Group sums, scans
+// and the slot rotation move data between the G lanes of a cell with DPP
+// row operations (a cell's lanes lie inside one 16-lane row), not through LDS.
+//
+// DPP controls (GFX9 encoding): quad_perm [1,0,3,2] = 0xB1 and [2,3,0,1] =
+// 0x4E (xor 1, xor 2), row_shl:n = 0x100 + n, row_shr:n = 0x110 + n,
+// row_mirror = 0x140, row_half_mirror = 0x141.  Lanes whose source falls
+// outside the row read 0 (bound_ctrl).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+
+// Sum over the G lanes of the group, the same value in every lane: xor-1 and
+// xor-2 pairs give quad sums, the half-row mirror pairs the two quads of an
+// 8-lane half, the row mirror the two halves of a row.
 template <typename T, int G>
 __device__ __forceinline__ T gsum(T x) {
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) x += __shfl_xor(x, d, G);
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    x += dpp<0x141>(x);
+    if (G == 16) x += dpp<0x140>(x);
     return x;
 }
+// Inclusive scan over the group (lane = index within the group).
 template <typename T, int G>
-__device__ __forceinline__ T gscan(T x, int lane) {  // inclusive
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-        const T y = __shfl_up(x, d, G);
-        if (lane >= d) x += y;
+__device__ __forceinline__ T gscan(T x, int lane) {
+    T y = dpp<0x111>(x);
+    x += lane >= 1 ? y : T(0);
+    y = dpp<0x112>(x);
+    x += lane >= 2 ? y : T(0);
+    y = dpp<0x114>(x);
+    x += lane >= 4 ? y : T(0);
+    if (G == 16) {
+        y = dpp<0x118>(x);
+        x += lane >= 8 ? y : T(0);
     }
     return x;
+}
+// Value of the previous lane of the group, cyclically (lane 0 reads lane G-1).
+template <typename T, int G>
+__device__ __forceinline__ T gprev(T x, int lane) {
+    const T a = dpp<0x111>(x);                      // row_shr:1
+    const T b = dpp<G == 16 ? 0x10F : 0x107>(x);    // row_shl:(G-1)
+    return lane == 0 ? b : a;
 }
 
 // t: thread index within the cell range (G lanes per cell, groups aligned).
@@ -164,11 +201,11 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     const T K = gsum<T, G>(kc * ue * ue);
     const T Sinc = gscan<T, G>(kf, lane);
     const T Sb = Sinc - kf;                      // S_b: fractions before slot b
-    const T Sn = __shfl(Sinc, G - 1, G);         // S_n
-    const T qt = T(0.5) * (__shfl(qv, (lane + G - 1) & (G - 1), G) + qv);
+    const T Sn = gsum<T, G>(kf);                 // S_n
+    const T qt = T(0.5) * (gprev<T, G>(qv, lane) + qv);
     const T X1 = Ga, X2 = Ga * qt;
     const T c1 = gscan<T, G>(X1, lane), c2 = gscan<T, G>(X2, lane);
-    const T t1 = __shfl(c1, G - 1, G), t2 = __shfl(c2, G - 1, G);  // sums; t1 = sum G
+    const T t1 = gsum<T, G>(X1), t2 = gsum<T, G>(X2);  // sums; t1 = sum G
     const T p1 = gsum<T, G>(Sb * X1), p2 = gsum<T, G>(Sb * X2);
     const T P1 = (Sb - T(0.5)) * (t1 - X1) - (p1 - Sb * X1) + Sn * (t1 - c1);
     const T P2 = (Sb - T(0.5)) * (t2 - X2) - (p2 - Sb * X2) + Sn * (t2 - c2);

@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["vr", "igw", "sphere", "ensemble", "surrogate"],
                     default="vr")
+    ap.add_argument("--case", choices=["jet", "tc5"], default="jet",
+                    help="sphere: balanced jet over random topography, or zonal flow over "
+                         "an isolated mountain")
     ap.add_argument("--trajectories", type=int, default=10,
                     help="surrogate: seeded training trajectories (the last 2 held out)")
     ap.add_argument("--traj-steps", type=int, default=200, help="surrogate: steps per trajectory")
@@ -135,7 +138,7 @@ def main():
 
     t0 = time.time()
     if args.workload == "sphere":
-        w = workloads.sphere_cap()
+        w = workloads.sphere_cap(case=args.case)
     else:
         w = workloads.vr_planar() if args.workload == "vr" else workloads.igw_hex()
     m = w.mesh

@@ -258,7 +258,32 @@ def sphere_state(m, u0=20.0, depth=5000.0, noise_rms=10.0, topo_rms=500.0, seed=
     return h, u
 
 
-def sphere_cap(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, M=4, progress=None) -> Workload:
+def tc5_state(m, u0=20.0, h0=5960.0, hs0=2000.0, g=9.81):
+    """Zonal flow over an isolated mountain (the standard shallow-water test
+    case 5): u = u0 cos(lat), surface h + b = h0 - (R Omega u0 + u0^2/2)
+    sin^2(lat) / g, conical mountain b = hs0 (1 - r / (pi/9)) with r the
+    (lon, lat) distance from (3 pi/2, pi/6), capped at pi/9.  Sets m.bottom;
+    returns (h, u)."""
+    from . import voronoi_sphere as vs
+    R, Om = vs.EARTH_RADIUS, vs.OMEGA
+    xc = np.stack([m.xCell, m.yCell, m.zCell], 1) / R
+    lat = np.arcsin(np.clip(xc[:, 2], -1, 1))
+    lon = np.mod(np.arctan2(xc[:, 1], xc[:, 0]), 2 * math.pi)
+    rm = math.pi / 9.0
+    r = np.minimum(rm, np.sqrt((lon - vs.CAP_LON) ** 2 + (lat - vs.CAP_LAT) ** 2))
+    b = hs0 * (1.0 - r / rm)
+    m.bottom = b
+    h = h0 - (R * Om * u0 + 0.5 * u0 * u0) * np.sin(lat) ** 2 / g - b
+    xe = np.stack([m.xEdge, m.yEdge, m.zEdge], 1) / R
+    late = np.arcsin(np.clip(xe[:, 2], -1, 1))
+    lone = np.arctan2(xe[:, 1], xe[:, 0])
+    east = np.stack([-np.sin(lone), np.cos(lone), np.zeros_like(lone)], 1)
+    u = u0 * np.cos(late) * np.einsum("ij,ij->i", east, m.normalEdge)
+    return h, u
+
+
+def sphere_cap(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, M=4, progress=None,
+               case="jet") -> Workload:
     """The variable-resolution sphere: n points Lloyd-relaxed `iters` times
     under rho ~ s^-4 with s 1 inside a 20-degree cap at (3 pi/2, pi/6) and 4
     outside (3-degree tanh transition), radius 6371 km, f = 2 Omega sin(lat);
@@ -271,10 +296,11 @@ def sphere_cap(n=SPH_N, seed=SPH_SEED, iters=SPH_ITERS, M=4, progress=None) -> W
     m = vs.sphere_voronoi_mesh(P, name=f"sphere{n}")
     xc = np.stack([m.xCell, m.yCell, m.zCell], 1) / vs.EARTH_RADIUS
     fm = (vs.cap_spacing_shape(xc) < 0.9 * vs.CAP_RATIO).astype(np.uint8)
-    h0, u0 = sphere_state(m, seed=seed)
+    h0, u0 = tc5_state(m) if case == "tc5" else sphere_state(m, seed=seed)
     spacing = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
     c = math.sqrt(9.81 * float((h0 + m.bottom).max())) + 20.0
     dt_fine = 0.3 * spacing.min() / c
-    return Workload(f"sphere-{n // 1000}k", m, fm, h0, u0, dt_fine * M, M,
+    name = f"sphere-{n // 1000}k" + ("-tc5" if case == "tc5" else "")
+    return Workload(name, m, fm, h0, u0, dt_fine * M, M,
                     extra=dict(dt_fine=dt_fine, spacing_min=float(spacing.min()),
                                spacing_max=float(spacing.max())))

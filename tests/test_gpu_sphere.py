@@ -99,6 +99,27 @@ def test_small_sphere_lts3_fp32(small):
     c.close()
 
 
+def test_small_sphere_tc5_fp64_and_fp32():
+    """Zonal flow over the isolated mountain on the 10k cap mesh: FP64 LTS3
+    against the oracle, FP32 within 1e-5, mass to 1e-13 (FP64)."""
+    w = workloads.sphere_cap(n=10_000, iters=25, case="tc5")
+    say("sphere10k tc5")
+    o = Oracle(w.mesh, w.gravity)
+    R = o.regions(w.fine_mask, w.n_if1, w.n_if2)
+    rh, ru = o.lts(w.h0, w.u0, w.dt_coarse, w.M, R, n=6)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        c = _ctx(w, prec)
+        c.init_state(w.h0, w.u0)
+        c.step(w.dt_coarse, w.M, 6)
+        gh, gu = c.get_state()
+        assert rel_l2(gh, rh, w.mesh.areaCell) < tol
+        assert rel_l2(gu, ru) < (1e-11 if prec == "fp64" else tol)
+        if prec == "fp64":
+            m0, _ = o.diagnostics(w.h0, w.u0)
+            assert abs(c.diagnostics().mass - m0) <= 1e-13 * m0
+        c.close()
+
+
 @pytest.fixture(scope="module")
 def full():
     w = workloads.sphere_cap()

@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["vr", "igw", "sphere", "ensemble", "surrogate"],
                     default="vr")
+    ap.add_argument("--layers", type=int, default=1,
+                    help="independent layers on the mesh (vertical batching; the layer-l state "
+                         "is the workload's perturbation scaled by 0.5 + l/L)")
     ap.add_argument("--case", choices=["jet", "tc5"], default="jet",
                     help="sphere: balanced jet over random topography, or zonal flow over "
                          "an isolated mountain")
@@ -152,25 +155,34 @@ def main():
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
     K, W, M, dt = args.steps, args.warmup, w.M, w.dt_coarse
+    L = args.layers
+    if L > 1:
+        H0 = float(np.median(w.h0))
+        sc = 0.5 + np.arange(L) / L
+        h0 = np.stack([H0 + (w.h0 - H0) * a for a in sc])
+        u0 = np.stack([w.u0 * a for a in sc])
+    else:
+        h0, u0 = w.h0, w.u0
+    wname = w.name if L == 1 else f"{w.name}-L{L}"
 
     def make(prec):
-        c = lts.LTSContext(0, prec, stream=sp)
+        c = lts.LTSContext(0, prec, stream=sp, layers=L)
         c.upload_mesh(m, w.fine_mask, w.n_if1, w.n_if2, w.gravity)
-        c.init_state(w.h0, w.u0)
+        c.init_state(h0, u0)
         return c
 
     ctx = make(prec)
     cells, edges, fbar = ctx.region_counts()
     ctx.step(dt, M, W)
-    ctx.init_state(w.h0, w.u0)
+    ctx.init_state(h0, u0)
     ms = timed(torch, stream, lambda: ctx.step(dt, M, K))
-    value = m.nCells * M * K / (ms / 1e3)
-    log(f"LTS3 {prec}: {ms / K:.3f} ms/coarse step, {value:.4e} cell-updates/s")
+    value = m.nCells * L * M * K / (ms / 1e3)
+    log(f"LTS3 {prec} x{L} layers: {ms / K:.3f} ms/coarse step, {value:.4e} cell-updates/s")
     d = ctx.diagnostics()
     h_lts, _ = ctx.get_state()
 
     # per-kernel timing pass (HIP events around every launch, same stream)
-    ctx.init_state(w.h0, w.u0)
+    ctx.init_state(h0, u0)
     ctx.set_timing(True)
     ctx.step(dt, M, K)
     stats = ctx.kernel_stats()
@@ -182,7 +194,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, w.name),
+                "traffic": measured_traffic(dom, wname),
                 "kernel": dom, "launches": st["launches"], "avg_us": round(avg_ms * 1e3, 2),
                 "bytes_per_launch": round(bytes_per_launch)}
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
@@ -194,7 +206,7 @@ def main():
            "steps": K, "warmup": W, "ms_per_step": round(ms / K, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32",
            "data": "synthetic",
-           "config": {"workload": w.name, "cells": m.nCells, "edges": m.nEdges,
+           "config": {"workload": wname, "cells": m.nCells, "layers": L, "edges": m.nEdges,
                       "vertices": m.nVertices, "M": M, "dt_coarse_s": round(dt, 6),
                       "interface_rings": [w.n_if1, w.n_if2],
                       "region_cells": {"F": int(cells[3]), "I1": int(cells[2]),
@@ -206,11 +218,16 @@ def main():
         # global SSPRK3 at the fine step over the same simulated time
         rk = make("fp64")
         rk.step_rk3(dt / M, W * M)
-        rk.init_state(w.h0, w.u0)
+        rk.init_state(h0, u0)
         ms_rk = timed(torch, stream, lambda: rk.step_rk3(dt / M, K * M))
-        v_rk = m.nCells * K * M / (ms_rk / 1e3)
+        v_rk = m.nCells * L * K * M / (ms_rk / 1e3)
         h_rk, _ = rk.get_state()
         log(f"SSPRK3 fp64 at dt/M: {ms_rk / K:.3f} ms per coarse-step interval, {v_rk:.4e}")
+        rk.close()
+    if not args.quick and L > 1:
+        out["comparisons"] = {"rk3_fp64_value": round(v_rk, 1),
+                              "lts3_over_rk3": round(value / v_rk, 3)}
+    if not args.quick and L == 1:
         # LTS3 in the other precision
         c32 = make(other)
         c32.step(dt, M, W)
@@ -243,7 +260,7 @@ def main():
                                                       + 3 * M * int(cells[3]) + int(fbar[0])), 3),
                               "l2_height_error": err,
                               "mass_rel_drift": None}
-        rk.close(), c32.close(), ref.close()
+        c32.close(), ref.close()
         ctx.init_state(w.h0, w.u0)
         d0 = ctx.diagnostics()
         out["comparisons"]["mass_rel_drift"] = abs(d.mass - d0.mass) / d0.mass
@@ -264,6 +281,23 @@ def main():
                                "sample": f"{n_cpu} LTS3 coarse steps (M={M}) of {w.name} in "
                                          f"{tc:.1f}s on {os.cpu_count()} host cores (1 used)"}
         log(f"cpu baseline: {out['cpu_baseline']}")
+    if not args.quick and L > 1:
+        # the oracle has no layers: one layer's rate is the per cell-layer rate
+        from oracle import Oracle
+        o = Oracle(m, w.gravity)
+        R = o.regions(w.fine_mask, w.n_if1, w.n_if2)
+        t1 = time.time()
+        o.lts(w.h0, w.u0, dt, M, R, n=1)
+        one = time.time() - t1
+        n_cpu = max(1, int(args.cpu_seconds / max(one, 1e-3)))
+        t1 = time.time()
+        o.lts(w.h0, w.u0, dt, M, R, n=n_cpu)
+        tc = time.time() - t1
+        out["cpu_baseline"] = {"value": round(m.nCells * M * n_cpu / tc, 1),
+                               "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n_cpu} single-layer LTS3 coarse steps (M={M}) of "
+                                         f"{w.name} in {tc:.1f}s on {os.cpu_count()} host cores "
+                                         f"(1 used)"}
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -96,6 +96,17 @@ typedef struct {
    context-owned stream. */
 lts_status lts_create(lts_ctx **out, int device, lts_precision prec, void *hip_stream);
 
+/* Advance n_layers independent copies of the system on the same mesh (the
+   vertical layers of an ocean-like workload; default 1).  Call before
+   lts_upload_mesh (LTS_ESTATE afterwards).  With L layers every state array
+   passed to or returned by the library (lts_init_state, lts_get_state,
+   lts_eval_rhs and their device forms) holds the L fields one after another:
+   h[l * n_cells + i], u[l * n_edges + e].  Diagnostics sum or reduce over all
+   layers.  On the device each per-element array is [element][layer], so a
+   wave works on consecutive layers of one element and reads its mesh
+   coefficients once. */
+lts_status lts_set_layers(lts_ctx *ctx, int n_layers);
+
 /* Validate and upload the mesh, label the LTS regions (F = cells with
    fine_mask != 0; I1 = n_if1_rings breadth-first cell rings around F; I2 = the
    next n_if2_rings; C = the rest; underlined F = the two fine rings nearest

@@ -247,13 +247,15 @@ lts_status set_reference(lts_ctx* c, double Hs) {
     return LTS_OK;
 }
 
-// Reference surface from a state in device order: area-weighted mean of h + b.
+// Reference surface from a state in device order ([cell][layer]):
+// area-weighted mean of h + b over all layers.
 double mean_surface(const lts_ctx* c, const std::vector<double>& h) {
     double num = 0.0, den = 0.0;
-    for (int i = 0; i < c->nC; ++i) {
-        num += c->area_perm[i] * (h[i] + c->bot_perm[i]);
-        den += c->area_perm[i];
-    }
+    for (int i = 0; i < c->nC; ++i)
+        for (int l = 0; l < c->L; ++l) {
+            num += c->area_perm[i] * (h[(size_t)i * c->L + l] + c->bot_perm[i]);
+            den += c->area_perm[i];
+        }
     return num / den;
 }
 
@@ -352,7 +354,8 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     if ((s = upload_vec<T>(c, &dm->kite, conv<T>(kite)))) return s;
     if ((s = upload_vec<T>(c, &dm->fA, conv<T>(fA)))) return s;
 
-    const size_t ts = sizeof(T);
+    // every per-element buffer holds L layers
+    const size_t ts = sizeof(T) * (size_t)c->L;
     const int nI1c = c->cb[4] - c->cb[3], nI1e = c->eb[3] - c->eb[2];
     const int nIc = c->cb[5] - c->cb[3], nIe = c->eb[4] - c->eb[2];
     void** bufs[] = {&c->Ah, &c->Bh, &c->Ch};
@@ -368,7 +371,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     void* fp = nullptr;
     if ((s = dalloc(c, &fp, 64))) return s;
     c->flag = static_cast<int*>(fp);
-    const int nblk = diag_blocks(nC) + diag_blocks(nE);
+    const int nblk = diag_blocks(nC * c->L) + diag_blocks(nE * c->L);
     void* pp = nullptr;
     if ((s = dalloc(c, &pp, (size_t)nblk * 8 * sizeof(double)))) return s;
     c->dpart = static_cast<double*>(pp);
@@ -498,15 +501,45 @@ lts_status run_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     return LTS_OK;
 }
 
+// Host state arrays hold the L layers one after another (layer-major, caller
+// numbering); device arrays are [element][layer] in device order.
+template <typename T>
+void to_device(const lts_ctx* c, const double* h, const double* u, std::vector<T>& hh,
+               std::vector<T>& uu) {
+    const int nC = c->nC, nE = c->nE, L = c->L;
+    hh.resize((size_t)nC * L);
+    uu.resize((size_t)nE * L);
+    for (int ni = 0; ni < nC; ++ni)
+        for (int l = 0; l < L; ++l)
+            hh[(size_t)ni * L + l] =
+                (T)(h[(size_t)l * nC + c->cperm[ni]] - (c->pert ? c->href_host[ni] : 0.0));
+    for (int ne = 0; ne < nE; ++ne)
+        for (int l = 0; l < L; ++l) uu[(size_t)ne * L + l] = (T)u[(size_t)l * nE + c->eperm[ne]];
+}
+
+template <typename T>
+void from_device(const lts_ctx* c, const std::vector<T>& hh, const std::vector<T>& uu, double* h,
+                 double* u, bool add_ref) {
+    const int nC = c->nC, nE = c->nE, L = c->L;
+    if (h)
+        for (int ni = 0; ni < nC; ++ni)
+            for (int l = 0; l < L; ++l)
+                h[(size_t)l * nC + c->cperm[ni]] =
+                    (double)hh[(size_t)ni * L + l] + (add_ref && c->pert ? c->href_host[ni] : 0.0);
+    if (u)
+        for (int ne = 0; ne < nE; ++ne)
+            for (int l = 0; l < L; ++l)
+                u[(size_t)l * nE + c->eperm[ne]] = (double)uu[(size_t)ne * L + l];
+}
+
 template <typename T>
 lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, double* du) {
     const int nC = c->nC, nE = c->nE;
-    std::vector<T> hh(nC), uu(nE);
-    for (int ni = 0; ni < nC; ++ni)
-        hh[ni] = (T)(h[c->cperm[ni]] - (c->pert ? c->href_host[ni] : 0.0));
-    for (int ne = 0; ne < nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
-    HIPCHK(c, hipMemcpyAsync(c->Bh, hh.data(), nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->Bu, uu.data(), nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    const size_t L = c->L;
+    std::vector<T> hh, uu;
+    to_device<T>(c, h, u, hh, uu);
+    HIPCHK(c, hipMemcpyAsync(c->Bh, hh.data(), nC * L * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->Bu, uu.data(), nE * L * sizeof(T), hipMemcpyHostToDevice, c->stream));
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
     Run<T> r{c, dm, c->stream, false};
     const Seg<T> none;
@@ -514,51 +547,48 @@ lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, do
                            Run<T>::upd(0, nC, (T*)c->Ch, nullptr, 0, nullptr, 0, 1.0), none,
                            Run<T>::upd(0, nE, (T*)c->Cu, nullptr, 0, nullptr, 0, 1.0), none);
     if (st) return st;
-    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ch, nC * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Cu, nE * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ch, nC * L * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Cu, nE * L * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int ni = 0; ni < nC; ++ni) dh[c->cperm[ni]] = (double)hh[ni];
-    for (int ne = 0; ne < nE; ++ne) du[c->eperm[ne]] = (double)uu[ne];
+    from_device<T>(c, hh, uu, dh, du, false);
     // eval_rhs clobbers the stage buffers: force the next step to re-capture
     return LTS_OK;
 }
 
 template <typename T>
 lts_status set_state(lts_ctx* c, const double* h, const double* u) {
-    std::vector<T> hh(c->nC), uu(c->nE);
+    const size_t L = c->L;
     if (c->pert) {
-        std::vector<double> hp(c->nC);
-        for (int ni = 0; ni < c->nC; ++ni) hp[ni] = h[c->cperm[ni]];
+        std::vector<double> hp((size_t)c->nC * L);
+        for (int ni = 0; ni < c->nC; ++ni)
+            for (size_t l = 0; l < L; ++l) hp[ni * L + l] = h[l * c->nC + c->cperm[ni]];
         lts_status s = set_reference<T>(c, mean_surface(c, hp));
         if (s) return s;
     }
-    for (int ni = 0; ni < c->nC; ++ni)
-        hh[ni] = (T)(h[c->cperm[ni]] - (c->pert ? c->href_host[ni] : 0.0));
-    for (int ne = 0; ne < c->nE; ++ne) uu[ne] = (T)u[c->eperm[ne]];
-    HIPCHK(c, hipMemcpyAsync(c->Ah, hh.data(), c->nC * sizeof(T), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->Au, uu.data(), c->nE * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    std::vector<T> hh, uu;
+    to_device<T>(c, h, u, hh, uu);
+    HIPCHK(c, hipMemcpyAsync(c->Ah, hh.data(), c->nC * L * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->Au, uu.data(), c->nE * L * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LTS_OK;
 }
 
 template <typename T>
 lts_status get_state(lts_ctx* c, double* h, double* u) {
-    std::vector<T> hh(c->nC), uu(c->nE);
-    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ah, c->nC * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Au, c->nE * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    const size_t L = c->L;
+    std::vector<T> hh((size_t)c->nC * L), uu((size_t)c->nE * L);
+    HIPCHK(c, hipMemcpyAsync(hh.data(), c->Ah, c->nC * L * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uu.data(), c->Au, c->nE * L * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (h)
-        for (int ni = 0; ni < c->nC; ++ni)
-            h[c->cperm[ni]] = (double)hh[ni] + (c->pert ? c->href_host[ni] : 0.0);
-    if (u) for (int ne = 0; ne < c->nE; ++ne) u[c->eperm[ne]] = (double)uu[ne];
+    from_device<T>(c, hh, uu, h, u, true);
     return LTS_OK;
 }
 
 template <typename T>
 lts_status diagnostics(lts_ctx* c, double out[8]) {
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
-    HIPCHK(c, launch_diag<T>(dm, (T*)c->Ah, (T*)c->Au, c->g, c->dpart, diag_blocks(c->nC),
-                             diag_blocks(c->nE), c->dout, c->stream));
+    HIPCHK(c, launch_diag<T>(dm, (T*)c->Ah, (T*)c->Au, c->g, c->dpart, diag_blocks(c->nC * c->L),
+                             diag_blocks(c->nE * c->L), c->dout, c->stream, c->L));
     int flag = 0;
     HIPCHK(c, hipMemcpyAsync(out, c->dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -619,6 +649,14 @@ void lts_destroy(lts_ctx* c) {
 }
 
 const char* lts_last_error(const lts_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lts_status lts_set_layers(lts_ctx* c, int n_layers) {
+    if (!c) return LTS_EINVAL;
+    if (n_layers < 1) return fail(c, LTS_EINVAL, "need n_layers >= 1");
+    if (c->has_mesh) return fail(c, LTS_ESTATE, "set the layer count before uploading the mesh");
+    c->L = n_layers;
+    return LTS_OK;
+}
 
 }  // extern "C"
 
@@ -815,14 +853,15 @@ lts_status lts_init_state_device(lts_ctx* c, const void* dh, const void* du, dou
     lts_status s = ready(c, false);
     if (s) return s;
     if (!dh || !du) return fail(c, LTS_EINVAL, "NULL state");
-    std::vector<double> h(c->nC), u(c->nE);
+    const size_t nh = (size_t)c->nC * c->L, nu = (size_t)c->nE * c->L;
+    std::vector<double> h(nh), u(nu);
     if (c->prec == LTS_FP64) {
-        HIPCHK(c, hipMemcpy(h.data(), dh, c->nC * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(u.data(), du, c->nE * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(h.data(), dh, nh * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(u.data(), du, nu * sizeof(double), hipMemcpyDeviceToHost));
     } else {
-        std::vector<float> hf(c->nC), uf(c->nE);
-        HIPCHK(c, hipMemcpy(hf.data(), dh, c->nC * sizeof(float), hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(uf.data(), du, c->nE * sizeof(float), hipMemcpyDeviceToHost));
+        std::vector<float> hf(nh), uf(nu);
+        HIPCHK(c, hipMemcpy(hf.data(), dh, nh * sizeof(float), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(uf.data(), du, nu * sizeof(float), hipMemcpyDeviceToHost));
         std::copy(hf.begin(), hf.end(), h.begin());
         std::copy(uf.begin(), uf.end(), u.begin());
     }
@@ -838,7 +877,7 @@ lts_status lts_step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
     if (n == 0) return LTS_OK;
     if (scheme == SCH_RK4 && !c->Qh) {
-        const size_t ts = tsize(c);
+        const size_t ts = tsize(c) * (size_t)c->L;
         if ((s = dalloc(c, &c->Qh, c->nC * ts)) || (s = dalloc(c, &c->Qu, c->nE * ts))) return s;
         HIPCHK(c, hipMemset(c->Qh, 0, c->nC * ts));
         HIPCHK(c, hipMemset(c->Qu, 0, c->nE * ts));
@@ -897,15 +936,16 @@ lts_status lts_get_state_device(lts_ctx* c, void* dh, void* du) {
     lts_status s = ready(c, true);
     if (s) return s;
     if (!dh || !du) return fail(c, LTS_EINVAL, "NULL output");
-    std::vector<double> h(c->nC), u(c->nE);
+    const size_t nh = (size_t)c->nC * c->L, nu = (size_t)c->nE * c->L;
+    std::vector<double> h(nh), u(nu);
     if ((s = lts_get_state(c, h.data(), u.data()))) return s;
     if (c->prec == LTS_FP64) {
-        HIPCHK(c, hipMemcpy(dh, h.data(), c->nC * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(du, u.data(), c->nE * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(dh, h.data(), nh * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(du, u.data(), nu * sizeof(double), hipMemcpyHostToDevice));
     } else {
         std::vector<float> hf(h.begin(), h.end()), uf(u.begin(), u.end());
-        HIPCHK(c, hipMemcpy(dh, hf.data(), c->nC * sizeof(float), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(du, uf.data(), c->nE * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(dh, hf.data(), nh * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(du, uf.data(), nu * sizeof(float), hipMemcpyHostToDevice));
     }
     return LTS_OK;
 }

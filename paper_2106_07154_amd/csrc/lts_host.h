@@ -50,6 +50,7 @@ struct lts_ctx {
 
     bool has_mesh = false, has_state = false, nonfinite = false;
     int nC = 0, nE = 0, nV = 0, maxE = 0;
+    int L = 1;  // independent layers; per-element device arrays are [element][L]
     double g = 9.81;
     std::vector<int32_t> cperm, cinv, eperm, einv, vperm, vinv;  // perm: new->old, inv: old->new
     std::vector<int8_t> creg, ereg;                              // caller numbering
@@ -138,16 +139,20 @@ double seg_bytes(const Seg<T>& g) {
     return b;
 }
 
+// With L layers the mesh tables count once and every state term L times (aux
+// counts are already in flat element x layer units).
 template <typename T>
 double kernel_bytes(const PassPlan& P, int kclass, const Seg<T>& s0, const Seg<T>& s1,
-                    const Aux<T>& aux) {
+                    const Aux<T>& aux, int L = 1) {
     const double ts = sizeof(T);
     if (kclass == KC_VERTEX)
-        return (P.v_hi - P.v_lo) * (3 * 4 * 2 + 8 * ts) + (P.v_uniq_u + P.v_uniq_h) * ts;
+        return (P.v_hi - P.v_lo) * (3 * 4 * 2 + 7 * ts) +
+               L * ((P.v_hi - P.v_lo) * ts + (P.v_uniq_u + P.v_uniq_h) * ts);
     if (kclass == KC_CELL)
-        return (P.c_hi - P.c_lo) * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts + ts) +
-               (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts + seg_bytes(s0) + seg_bytes(s1);
-    return (P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(s0) + seg_bytes(s1) +
+        return (P.c_hi - P.c_lo) * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts) +
+               L * (P.c_slots * ts + (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts +
+                    seg_bytes(s0) + seg_bytes(s1));
+    return L * ((P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(s0) + seg_bytes(s1)) +
            (aux.kind == 1 ? 4.0 : aux.kind == 2 ? 3.0 : 0.0) * (aux.nh + aux.nu) * ts;
 }
 
@@ -193,6 +198,21 @@ struct Run {
         T* zs = static_cast<T*>(c->zs);
         hipEvent_t e0, e1;
         lts_status st;
+        if (c->L > 1) {  // layered: one thread per (element, layer)
+            const int L = c->L;
+            if ((st = events(&e0, &e1))) return st;
+            HIPCHK(c, launch_vertex_l<T>(dm, h, u, q, P.v_lo, P.v_hi, L, s, e0, e1));
+            done(KC_VERTEX, e0, e1, kernel_bytes<T>(P, KC_VERTEX, cs0, cs1, aux, L));
+            if ((st = events(&e0, &e1))) return st;
+            HIPCHK(c, launch_cell_l<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, L, (T)c->g, cs0, cs1,
+                                       c->flag, s, e0, e1));
+            done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux, L));
+            if ((st = events(&e0, &e1))) return st;
+            HIPCHK(c, launch_edge_l<T>(zs, c->nE, P.et_lo, P.et_hi, L, es0, es1, aux, c->flag, s,
+                                       e0, e1));
+            done(KC_EDGE, e0, e1, kernel_bytes<T>(P, KC_EDGE, es0, es1, aux, L));
+            return LTS_OK;
+        }
         // vertex PV, or evaluated by the cell kernel itself (see fuse_q)
         const bool fuse = c->fuse_q == 2 || (c->fuse_q == 1 && P.c_hi - P.c_lo <= kFuseQCells);
         if (!fuse) {
@@ -244,10 +264,10 @@ struct Run {
         double cf[3];
         predict_coeffs(stage, k, M, cf, order);
         x.kind = 1;
-        x.nh = c->cb[4] - c->cb[3];
-        x.nu = c->eb[3] - c->eb[2];
-        x.lo_h = c->cb[3];
-        x.lo_u = c->eb[2];
+        x.nh = (c->cb[4] - c->cb[3]) * c->L;  // flat element x layer units
+        x.nu = (c->eb[3] - c->eb[2]) * c->L;
+        x.lo_h = c->cb[3] * c->L;
+        x.lo_u = c->eb[2] * c->L;
         x.xh = xh;
         x.xu = xu;
         x.ah = (T*)c->x0h; x.bh = (T*)c->x1h; x.ch = (T*)c->x2h;
@@ -258,12 +278,12 @@ struct Run {
     Aux<T> correct_aux(double delta) {
         Aux<T> x;
         x.kind = 2;
-        x.nh = c->cb[5] - c->cb[3];
-        x.nu = c->eb[4] - c->eb[2];
-        x.nbh = c->cb[4] - c->cb[3];
-        x.nbu = c->eb[3] - c->eb[2];
-        x.lo_h = c->cb[3];
-        x.lo_u = c->eb[2];
+        x.nh = (c->cb[5] - c->cb[3]) * c->L;  // flat element x layer units
+        x.nu = (c->eb[4] - c->eb[2]) * c->L;
+        x.nbh = (c->cb[4] - c->cb[3]) * c->L;
+        x.nbu = (c->eb[3] - c->eb[2]) * c->L;
+        x.lo_h = c->cb[3] * c->L;
+        x.lo_u = c->eb[2] * c->L;
         x.xh = (T*)c->Ah;
         x.xu = (T*)c->Au;
         x.ah = (T*)c->x0h; x.bh = (T*)c->acch;

@@ -124,7 +124,23 @@ __host__ __device__ inline int padded_slots(int maxE) { return maxE <= 8 ? 8 : 1
 // then a single-block deterministic reduction into out[8] (doubles).
 template <typename T>
 hipError_t launch_diag(const DevMesh<T>& m, const T* h, const T* u, double g, double* part,
-                       int nblk_cells, int nblk_edges, double* out, hipStream_t s);
+                       int nblk_cells, int nblk_edges, double* out, hipStream_t s, int L = 1);
+// Layered forms (L independent layers, every per-element array [element][L]):
+// the same passes with one thread per (element, layer).  Aux counts and
+// offsets are given in flat (element x layer) units.
+template <typename T>
+hipError_t launch_vertex_l(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo,
+                           int v_hi, int L, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
+template <typename T>
+hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs,
+                         int c_lo, int c_hi, int L, T g, const Seg<T>& s0, const Seg<T>& s1,
+                         int* flag, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
+template <typename T>
+hipError_t launch_edge_l(const T* zs, int nE, int lo, int hi, int L, const Seg<T>& s0,
+                         const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int diag_blocks(int n);
 hipError_t launch_fill_int(int* p, int v, hipStream_t s);
 

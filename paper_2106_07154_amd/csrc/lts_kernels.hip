@@ -327,20 +327,21 @@ __global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_diag_part(DevMesh<T> m, const T* __restrict__ h,
                                                       const T* __restrict__ u, double g,
-                                                      double* part, int nblk_cells) {
+                                                      double* part, int nblk_cells, int L) {
     __shared__ double red[6][kBlock];
     const int t = threadIdx.x;
     double v[6] = {0.0, 0.0, -1e300, -1e300, 0.0, 0.0};
     if ((int)blockIdx.x < nblk_cells) {
-        const int i = blockIdx.x * kBlock + t;
+        const long il = (long)blockIdx.x * kBlock + t;
+        const int i = (int)(il / L), l = (int)(il % L);
         if (i < m.nC) {
-            const double hi = m.href ? (double)m.href[i] + (double)h[i] : (double)h[i];
+            const double hi = m.href ? (double)m.href[i] + (double)h[il] : (double)h[il];
             double K = 0.0;
             const int n = m.nEoC[i];
             const int G = padded_slots(m.maxE);
             for (int a = 0; a < n; ++a) {
                 const size_t o = (size_t)i * G + a;
-                const double ue = (double)u[m.eoc[o]];
+                const double ue = (double)u[(size_t)m.eoc[o] * L + l];
                 K += (double)m.kc[o] * ue * ue;
             }
             const double A = (double)m.area[i];
@@ -351,8 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_part(DevMesh<T> m, const T* __r
             v[5] = isfinite(hi) ? 0.0 : 1.0;
         }
     } else {
-        const int e = (blockIdx.x - nblk_cells) * kBlock + t;
-        if (e < m.nE) {
+        const long e = (long)(blockIdx.x - nblk_cells) * kBlock + t;
+        if (e < (long)m.nE * L) {
             const double ue = (double)u[e];
             v[4] = fabs(ue);
             v[5] = isfinite(ue) ? 0.0 : 1.0;
@@ -408,6 +409,151 @@ __global__ void k_fill_int(int* p, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) p[threadIdx.x] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Layered kernels: L independent layers on one mesh (the vertical dimension of
+// an ocean-like workload).  Every per-element array is [element][layer],
+// layer fastest, so consecutive threads are consecutive layers of the same
+// element: the mesh tables are read once per element and broadcast to its
+// layers, and the state accesses of a wave are contiguous.
+
+// apply_seg for element j, layer l: the same arithmetic on the flat index
+// j L + l (segment ranges stay in elements).
+template <typename T>
+__device__ __forceinline__ void apply_seg_l(int j, int l, int L, T G, const Seg<T>& s,
+                                            int* flag) {
+    const size_t f = (size_t)j * L + l;
+    T v;
+    if (s.mode == 1) {
+        v = s.a_dt * G;
+        if (s.xold) v = s.a_old * s.xold[f] + (s.xcur ? s.a_cur * s.xcur[f] : T(0)) + v;
+        else if (s.xcur) v = s.a_cur * s.xcur[f] + v;
+        s.out[f] = v;
+        if (j >= s.mlo && j < s.mhi) {
+            const size_t fm = (size_t)(j - s.mlo) * L + l;
+            if (s.mnew) s.mnew[fm] = v;
+            if (s.mcur) s.mcur[fm] = s.xcur[f];
+        }
+        if (s.acc) {
+            const size_t k = (size_t)(j - s.lo) * L + l;
+            const T a = s.theta * G;
+            s.acc[k] = s.first ? a : s.acc[k] + a;
+        }
+    } else {
+        const size_t k = (size_t)(j - s.lo) * L + l;
+        v = s.theta * G;
+        if (!s.first) v = s.acc[k] + v;
+        s.acc[k] = v;
+    }
+    if (!isfinite(v)) flag[0] = 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void epilogue_l(int j, int l, int L, T G, const Seg<T>& s0,
+                                           const Seg<T>& s1, int* flag) {
+    if (s0.mode && j >= s0.lo && j < s0.hi) apply_seg_l(j, l, L, G, s0, flag);
+    else if (s1.mode && j >= s1.lo && j < s1.hi) apply_seg_l(j, l, L, G, s1, flag);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __restrict__ h,
+                                                     const T* __restrict__ u,
+                                                     T* __restrict__ q, int v_lo, int v_hi,
+                                                     int L) {
+    const long t = (long)xcd_block() * kBlock + threadIdx.x;
+    const int v = v_lo + (int)(t / L), l = (int)(t % L);
+    if (v >= v_hi) return;
+    const int nV = m.nV;
+    T circ = 0, hv = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int o = k * nV + v;
+        const int c = m.cov[o];
+        const T hc = h[(size_t)c * L + l];
+        circ += m.tdc[o] * u[(size_t)m.eov[o] * L + l];
+        hv += m.kite[o] * (m.href ? m.href[c] + hc : hc);
+    }
+    q[(size_t)v * L + l] = (m.fA[v] + circ) / hv;
+}
+
+// One thread per (cell, layer); the cell's slots in a loop, with the same
+// O(n) prefix-sum form of the PV share as the single-layer cell kernel.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __restrict__ h,
+                                                   const T* __restrict__ u,
+                                                   const T* __restrict__ q,
+                                                   T* __restrict__ zs, int c_lo, int c_hi,
+                                                   int L, T g, Seg<T> s0, Seg<T> s1,
+                                                   int* flag) {
+    const long t = (long)xcd_block() * kBlock + threadIdx.x;
+    const int i = c_lo + (int)(t / L), l = (int)(t % L);
+    if (i >= c_hi) return;
+    const T* __restrict__ href = m.href;
+    const int n = m.nEoC[i];
+    const size_t il = (size_t)i * L + l;
+    const T hi = href ? href[i] + h[il] : h[il];
+    // PV of the last slot's vertex: the predecessor of slot 0
+    T qprev = q[(size_t)m.voc[(size_t)i * G + n - 1] * L + l];
+    T X1[G], X2[G], Sb[G], nd[G], qtA[G];
+    int ed[G];
+    T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (a < n) {
+            const size_t o = (size_t)i * G + a;
+            const int e = m.eoc[o], nb = m.coc[o];
+            const T ue = u[(size_t)e * L + l];
+            const T hn0 = h[(size_t)nb * L + l];
+            const T hn = href ? href[nb] + hn0 : hn0;
+            const T qa = q[(size_t)m.voc[o] * L + l];
+            const T qt = T(0.5) * (qprev + qa);
+            qprev = qa;
+            X1[a] = m.nl[o] * (T(0.5) * (hi + hn) * ue);
+            X2[a] = X1[a] * qt;
+            qtA[a] = qt;
+            K += m.kc[o] * ue * ue;
+            Sb[a] = S;
+            S += m.kf[o];
+            nd[a] = m.nd[o];
+            ed[a] = e;
+            t1 += X1[a];
+            t2 += X2[a];
+            p1 += Sb[a] * X1[a];
+            p2 += Sb[a] * X2[a];
+        }
+    }
+    const T phi = g * (h[il] + m.beta[i]) + K;
+    T c1 = 0, c2 = 0;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (a < n) {
+            c1 += X1[a];
+            c2 += X2[a];
+            const T P1 = (Sb[a] - T(0.5)) * (t1 - X1[a]) - (p1 - Sb[a] * X1[a]) + S * (t1 - c1);
+            const T P2 = (Sb[a] - T(0.5)) * (t2 - X2[a]) - (p2 - Sb[a] * X2[a]) + S * (t2 - c2);
+            zs[(nd[a] > T(0) ? 0 : (size_t)m.nE * L) + (size_t)ed[a] * L + l] =
+                nd[a] * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
+        }
+    }
+    epilogue_l(i, l, L, -t1 / m.area[i], s0, s1, flag);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_edge_l(const T* __restrict__ zs, int nE, int lo,
+                                                   int hi, int L, int nbe, Seg<T> s0, Seg<T> s1,
+                                                   Aux<T> aux, int* flag) {
+    if ((int)blockIdx.x >= nbe) {
+        run_aux(aux, (blockIdx.x - nbe) * kBlock + threadIdx.x);
+        return;
+    }
+    const int b = blockIdx.x, x = b & 7, k = b >> 3, qq = nbe >> 3, r = nbe & 7;
+    const int lb = x < r ? x * (qq + 1) + k : r * (qq + 1) + (x - r) * qq + k;
+    const long t = (long)lb * kBlock + threadIdx.x;
+    const int e = lo + (int)(t / L), l = (int)(t % L);
+    if (e >= hi) return;
+    const size_t f = (size_t)e * L + l;
+    epilogue_l(e, l, L, zs[f] + zs[(size_t)nE * L + f], s0, s1, flag);
+}
+
 inline unsigned nblocks(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -455,6 +601,38 @@ hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, co
 }
 
 template <typename T>
+hipError_t launch_vertex_l(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo, int v_hi,
+                           int L, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (v_hi <= v_lo) return hipSuccess;
+    return launch(k_vertex_l<T>, dim3(nblocks((long)(v_hi - v_lo) * L)), s, ev0, ev1, m, h, u, q,
+                  v_lo, v_hi, L);
+}
+
+template <typename T>
+hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs,
+                         int c_lo, int c_hi, int L, T g, const Seg<T>& s0, const Seg<T>& s1,
+                         int* flag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (c_hi <= c_lo) return hipSuccess;
+    const dim3 grid(nblocks((long)(c_hi - c_lo) * L));
+    if (padded_slots(m.maxE) == 8)
+        return launch(k_cell_l<T, 8>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,
+                      flag);
+    return launch(k_cell_l<T, 16>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,
+                  flag);
+}
+
+template <typename T>
+hipError_t launch_edge_l(const T* zs, int nE, int lo, int hi, int L, const Seg<T>& s0,
+                         const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+    const int nbe = hi > lo ? (int)nblocks((long)(hi - lo) * L) : 0;
+    const int nba = aux.kind ? (int)nblocks((long)aux.nh + aux.nu) : 0;
+    if (nbe + nba == 0) return hipSuccess;
+    return launch(k_edge_l<T>, dim3(nbe + nba), s, ev0, ev1, zs, nE, lo, hi, L, nbe, s0, s1, aux,
+                  flag);
+}
+
+template <typename T>
 hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, int block, int grid,
                         int G, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (nvb <= 0) return hipSuccess;
@@ -483,9 +661,9 @@ hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, i
 
 template <typename T>
 hipError_t launch_diag(const DevMesh<T>& m, const T* h, const T* u, double g, double* part,
-                       int nblk_cells, int nblk_edges, double* out, hipStream_t s) {
+                       int nblk_cells, int nblk_edges, double* out, hipStream_t s, int L) {
     hipLaunchKernelGGL(k_diag_part<T>, dim3(nblk_cells + nblk_edges), dim3(kBlock), 0, s, m, h,
-                       u, g, part, nblk_cells);
+                       u, g, part, nblk_cells, L);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, s, part, nblk_cells + nblk_edges,
@@ -509,7 +687,15 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
     template hipError_t launch_batch<T>(int, const Item<T>*, int, int, int, int, int,           \
                                         hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_diag<T>(const DevMesh<T>&, const T*, const T*, double, double*,   \
-                                       int, int, double*, hipStream_t);
+                                       int, int, double*, hipStream_t, int);                     \
+    template hipError_t launch_vertex_l<T>(const DevMesh<T>&, const T*, const T*, T*, int, int,  \
+                                           int, hipStream_t, hipEvent_t, hipEvent_t);            \
+    template hipError_t launch_cell_l<T>(const DevMesh<T>&, const T*, const T*, const T*, T*,    \
+                                         int, int, int, T, const Seg<T>&, const Seg<T>&, int*,   \
+                                         hipStream_t, hipEvent_t, hipEvent_t);                   \
+    template hipError_t launch_edge_l<T>(const T*, int, int, int, int, const Seg<T>&,            \
+                                         const Seg<T>&, const Aux<T>&, int*, hipStream_t,        \
+                                         hipEvent_t, hipEvent_t);
 
 LTS_INSTANTIATE(double)
 LTS_INSTANTIATE(float)

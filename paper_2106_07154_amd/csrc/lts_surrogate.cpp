@@ -391,6 +391,10 @@ lts_status lts_sur_create(lts_sur** out, lts_ctx* c, int n_layers, int hidden, u
         c->err = "surrogate: context needs a mesh and a state";
         return LTS_EINVAL;
     }
+    if (c->L != 1) {
+        c->err = "surrogate: single-layer contexts only";
+        return LTS_EINVAL;
+    }
     lts_sur* s = new lts_sur();
     s->c = c;
     s->dm_at_create = c->dm;

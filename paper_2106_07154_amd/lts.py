@@ -21,7 +21,7 @@ LTS_FP64, LTS_FP32 = 0, 1
 LTS_C, LTS_I2, LTS_I1, LTS_F = 0, 1, 2, 3
 KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency"]
 
-EXPORTED = ["lts_create", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
+EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
             "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_step_scheme", "lts_eval_rhs",
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "lts_create": ([PP, ci, ci, P], ci),
+        "lts_set_layers": ([P, ci], ci),
         "lts_upload_mesh": ([P, ctypes.POINTER(_Mesh), P, ci, ci, cd], ci),
         "lts_get_regions": ([P, P, P, P, P], ci),
         "lts_init_state": ([P, P, P, cd], ci),
@@ -149,9 +150,10 @@ def _ptr(a: np.ndarray) -> int:
 class LTSContext:
     """One liblts context: a mesh, its LTS regions and a state on one GPU."""
 
-    def __init__(self, device: int = 0, precision: str = "fp64", stream=None):
+    def __init__(self, device: int = 0, precision: str = "fp64", stream=None, layers: int = 1):
         self._lib = load_library()
         self.precision = precision
+        self.layers = int(layers)
         prec = {"fp64": LTS_FP64, "fp32": LTS_FP32}[precision]
         if stream is not None and not isinstance(stream, int):
             stream = stream.cuda_stream  # a torch.cuda.Stream
@@ -166,6 +168,8 @@ class LTSContext:
         self._h = h
         self._keep = []
         self.mesh = None
+        if self.layers != 1:
+            self._check(self._lib.lts_set_layers(self._h, self.layers))
 
     def _check(self, st: int):
         if st != LTS_OK:
@@ -218,9 +222,13 @@ class LTSContext:
                                                     u_tensor.data_ptr(), float(t0)))
 
     def get_state(self):
-        h = np.empty(self.mesh.nCells)
-        u = np.empty(self.mesh.nEdges)
+        """(h, u); with several layers, arrays of shape (layers, n)."""
+        L = self.layers
+        h = np.empty(self.mesh.nCells * L)
+        u = np.empty(self.mesh.nEdges * L)
         self._check(self._lib.lts_get_state(self._h, _ptr(h), _ptr(u)))
+        if L > 1:
+            return h.reshape(L, -1), u.reshape(L, -1)
         return h, u
 
     def get_state_device(self, h_tensor, u_tensor):

@@ -493,8 +493,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     const T hi = href ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
     T qprev = q[(size_t)m.voc[(size_t)i * G + n - 1] * L + l];
-    T X1[G], X2[G], Sb[G], nd[G], qtA[G];
-    int ed[G];
+    // per-slot values kept for the second loop; indices, kite fractions and
+    // 1/d_e are read again there (broadcast loads) to keep registers low
+    T X1[G], X2[G], qtA[G];
     T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
@@ -511,27 +512,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
             X2[a] = X1[a] * qt;
             qtA[a] = qt;
             K += m.kc[o] * ue * ue;
-            Sb[a] = S;
+            const T Sb = S;
             S += m.kf[o];
-            nd[a] = m.nd[o];
-            ed[a] = e;
             t1 += X1[a];
             t2 += X2[a];
-            p1 += Sb[a] * X1[a];
-            p2 += Sb[a] * X2[a];
+            p1 += Sb * X1[a];
+            p2 += Sb * X2[a];
         }
     }
     const T phi = g * (h[il] + m.beta[i]) + K;
-    T c1 = 0, c2 = 0;
+    T c1 = 0, c2 = 0, Sr = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
         if (a < n) {
+            const size_t o = (size_t)i * G + a;
+            const T Sb = Sr;
+            Sr += m.kf[o];
             c1 += X1[a];
             c2 += X2[a];
-            const T P1 = (Sb[a] - T(0.5)) * (t1 - X1[a]) - (p1 - Sb[a] * X1[a]) + S * (t1 - c1);
-            const T P2 = (Sb[a] - T(0.5)) * (t2 - X2[a]) - (p2 - Sb[a] * X2[a]) + S * (t2 - c2);
-            zs[(nd[a] > T(0) ? 0 : (size_t)m.nE * L) + (size_t)ed[a] * L + l] =
-                nd[a] * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
+            const T P1 = (Sb - T(0.5)) * (t1 - X1[a]) - (p1 - Sb * X1[a]) + S * (t1 - c1);
+            const T P2 = (Sb - T(0.5)) * (t2 - X2[a]) - (p2 - Sb * X2[a]) + S * (t2 - c2);
+            const T nd = m.nd[o];
+            zs[(nd > T(0) ? 0 : (size_t)m.nE * L) + (size_t)m.eoc[o] * L + l] =
+                nd * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
         }
     }
     epilogue_l(i, l, L, -t1 / m.area[i], s0, s1, flag);

@@ -259,11 +259,45 @@ def main():
                                   3 * M * m.nCells / (3 * int(cells[0]) + (2 + 3 * M) * int(cells[1] + cells[2])
                                                       + 3 * M * int(cells[3]) + int(fbar[0])), 3),
                               "l2_height_error": err,
+                              "time_to_solution": None,
                               "mass_rel_drift": None}
+        # time-to-solution at a fixed L2 height error: each method at several
+        # step sizes over the same simulated time; the fastest run that meets
+        # eps (twice the error of LTS3 at its operating point) counts
+        eps = 2.0 * err[f"lts3_{prec}"]
+
+        def at(kind, k):
+            c = make(prec if kind == "lts3" else "fp64")
+            n = K // k if kind == "lts3" else K * M // k
+            go = (lambda j: c.step(k * dt, M, j)) if kind == "lts3" else \
+                (lambda j: c.step_rk3(k * dt / M, j))
+            try:
+                go(1)                      # capture the step's graph outside the timing
+                c.init_state(h0, u0)
+                t = timed(torch, stream, lambda: go(n))
+                st, _ = c.diagnostics_status()
+                hk, _ = c.get_state()
+                e = rel_l2(hk - H, h_ref - H, wA) if st == 0 else float("inf")
+            except lts.LTSError:
+                t, e = None, float("inf")
+            c.close()
+            return {"step_factor": k, "steps": n, "ms": None if t is None else round(t, 3),
+                    "err": e}
+        tts = {"eps": eps, "lts3": [at("lts3", k) for k in (1, 2, 4, 5) if K % k == 0],
+               "rk3_fp64": [at("rk3", k) for k in (1, 2, 4, 5, 8) if (K * M) % k == 0]}
+        best = {}
+        for kind in ("lts3", "rk3_fp64"):
+            ok = [r["ms"] for r in tts[kind] if r["ms"] is not None and r["err"] <= eps]
+            best[kind] = min(ok) if ok else None
+        tts["best_ms"] = best
+        tts["rk3_over_lts3"] = (round(best["rk3_fp64"] / best["lts3"], 3)
+                                if best["lts3"] and best["rk3_fp64"] else None)
+        log("time to solution:", json.dumps(tts))
         c32.close(), ref.close()
         ctx.init_state(w.h0, w.u0)
         d0 = ctx.diagnostics()
         out["comparisons"]["mass_rel_drift"] = abs(d.mass - d0.mass) / d0.mass
+        out["comparisons"]["time_to_solution"] = tts
 
         # CPU baseline: the FP64 oracle, one thread, bounded sample
         from oracle import Oracle

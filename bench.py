@@ -268,7 +268,7 @@ def main():
 
         def at(kind, k):
             c = make(prec if kind == "lts3" else "fp64")
-            n = K // k if kind == "lts3" else K * M // k
+            n = round(K / k) if kind == "lts3" else round(K * M / k)
             go = (lambda j: c.step(k * dt, M, j)) if kind == "lts3" else \
                 (lambda j: c.step_rk3(k * dt / M, j))
             try:
@@ -281,10 +281,15 @@ def main():
             except lts.LTSError:
                 t, e = None, float("inf")
             c.close()
-            return {"step_factor": k, "steps": n, "ms": None if t is None else round(t, 3),
-                    "err": e}
-        tts = {"eps": eps, "lts3": [at("lts3", k) for k in (1, 2, 4, 5) if K % k == 0],
-               "rk3_fp64": [at("rk3", k) for k in (1, 2, 4, 5, 8) if (K * M) % k == 0]}
+            return {"step_factor": round(k, 4), "steps": n,
+                    "ms": None if t is None else round(t, 3), "err": e}
+
+        def whole(total, k):  # the factor gives a whole number of steps
+            return abs(total / k - round(total / k)) < 1e-9
+        factors = (1.0, 1.25, 4.0 / 3.0, 1.6, 2.0, 2.5, 3.2, 4.0, 5.0, 8.0)
+        tts = {"eps": eps,
+               "lts3": [at("lts3", k) for k in factors[:9] if whole(K, k)],
+               "rk3_fp64": [at("rk3", k) for k in factors if whole(K * M, k)]}
         best = {}
         for kind in ("lts3", "rk3_fp64"):
             ok = [r["ms"] for r in tts[kind] if r["ms"] is not None and r["err"] <= eps]

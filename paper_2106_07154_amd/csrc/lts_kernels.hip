@@ -454,66 +454,103 @@ __device__ __forceinline__ void epilogue_l(int j, int l, int L, T G, const Seg<T
     else if (s1.mode && j >= s1.lo && j < s1.hi) apply_seg_l(j, l, L, G, s1, flag);
 }
 
-template <typename T>
+// Thread-to-(element, layer) maps of the layered vertex and cell kernels.
+// W = false: one thread per pair, consecutive threads along the layers.
+// W = true: each wave takes one element and a chunk of 64 consecutive layers;
+// the element index is wave-uniform, so its mesh-table entries come in
+// through scalar loads and the vector memory instructions are the contiguous
+// state accesses only.  Lanes past the last layer compute on the last layer
+// and store nothing.
+template <bool W>
+__device__ __forceinline__ void layer_slot(int n_lo, int L, int& k, int& l, bool& act) {
+    const long t = (long)xcd_block() * kBlock + threadIdx.x;
+    if (!W) {
+        k = n_lo + (int)(t / L);
+        l = (int)(t % L);
+        act = true;
+        return;
+    }
+    const long wv = t >> 6;
+    const int nch = (L + 63) >> 6;
+    k = __builtin_amdgcn_readfirstlane(n_lo + (int)(wv / nch));
+    const int l0 = (int)(wv % nch) * 64 + (int)(threadIdx.x & 63);
+    act = l0 < L;
+    l = act ? l0 : L - 1;
+}
+
+template <typename T, bool W>
 __global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __restrict__ h,
                                                      const T* __restrict__ u,
                                                      T* __restrict__ q, int v_lo, int v_hi,
                                                      int L) {
-    const long t = (long)xcd_block() * kBlock + threadIdx.x;
-    const int v = v_lo + (int)(t / L), l = (int)(t % L);
+    int v, l;
+    bool act;
+    layer_slot<W>(v_lo, L, v, l, act);
     if (v >= v_hi) return;
     const int nV = m.nV;
+    const int32_t* __restrict__ cov = m.cov;
+    const int32_t* __restrict__ eov = m.eov;
+    const T* __restrict__ tdc = m.tdc;
+    const T* __restrict__ kite = m.kite;
+    const T* __restrict__ href = m.href;
     T circ = 0, hv = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int o = k * nV + v;
-        const int c = m.cov[o];
+        const int c = cov[o];
         const T hc = h[(size_t)c * L + l];
-        circ += m.tdc[o] * u[(size_t)m.eov[o] * L + l];
-        hv += m.kite[o] * (m.href ? m.href[c] + hc : hc);
+        circ += tdc[o] * u[(size_t)eov[o] * L + l];
+        hv += kite[o] * (href ? href[c] + hc : hc);
     }
-    q[(size_t)v * L + l] = (m.fA[v] + circ) / hv;
+    const T qv = (m.fA[v] + circ) / hv;
+    if (act) q[(size_t)v * L + l] = qv;
 }
 
-// One thread per (cell, layer); the cell's slots in a loop, with the same
-// O(n) prefix-sum form of the PV share as the single-layer cell kernel.
-template <typename T, int G>
+// The cell's slots in a loop, with the same O(n) prefix-sum form of the PV
+// share as the single-layer cell kernel.
+template <typename T, int G, bool W>
 __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __restrict__ h,
                                                    const T* __restrict__ u,
                                                    const T* __restrict__ q,
                                                    T* __restrict__ zs, int c_lo, int c_hi,
                                                    int L, T g, Seg<T> s0, Seg<T> s1,
                                                    int* flag) {
-    const long t = (long)xcd_block() * kBlock + threadIdx.x;
-    const int i = c_lo + (int)(t / L), l = (int)(t % L);
+    int i, l;
+    bool act;
+    layer_slot<W>(c_lo, L, i, l, act);
     if (i >= c_hi) return;
+    const int32_t* __restrict__ eoc = m.eoc;
+    const int32_t* __restrict__ coc = m.coc;
+    const int32_t* __restrict__ voc = m.voc;
+    const T* __restrict__ nl = m.nl;
+    const T* __restrict__ nd = m.nd;
+    const T* __restrict__ kc = m.kc;
+    const T* __restrict__ kf = m.kf;
     const T* __restrict__ href = m.href;
     const int n = m.nEoC[i];
     const size_t il = (size_t)i * L + l;
     const T hi = href ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
-    T qprev = q[(size_t)m.voc[(size_t)i * G + n - 1] * L + l];
-    // per-slot values kept for the second loop; indices, kite fractions and
-    // 1/d_e are read again there (broadcast loads) to keep registers low
+    T qprev = q[(size_t)voc[(size_t)i * G + n - 1] * L + l];
     T X1[G], X2[G], qtA[G];
     T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
         if (a < n) {
             const size_t o = (size_t)i * G + a;
-            const int e = m.eoc[o], nb = m.coc[o];
+            const int e = eoc[o], nb = coc[o];
             const T ue = u[(size_t)e * L + l];
             const T hn0 = h[(size_t)nb * L + l];
             const T hn = href ? href[nb] + hn0 : hn0;
-            const T qa = q[(size_t)m.voc[o] * L + l];
+            const T qa = q[(size_t)voc[o] * L + l];
             const T qt = T(0.5) * (qprev + qa);
             qprev = qa;
-            X1[a] = m.nl[o] * (T(0.5) * (hi + hn) * ue);
+            X1[a] = nl[o] * (T(0.5) * (hi + hn) * ue);
             X2[a] = X1[a] * qt;
             qtA[a] = qt;
-            K += m.kc[o] * ue * ue;
+            K += kc[o] * ue * ue;
             const T Sb = S;
-            S += m.kf[o];
+            S += kf[o];
             t1 += X1[a];
             t2 += X2[a];
             p1 += Sb * X1[a];
@@ -527,17 +564,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
         if (a < n) {
             const size_t o = (size_t)i * G + a;
             const T Sb = Sr;
-            Sr += m.kf[o];
+            Sr += kf[o];
             c1 += X1[a];
             c2 += X2[a];
             const T P1 = (Sb - T(0.5)) * (t1 - X1[a]) - (p1 - Sb * X1[a]) + S * (t1 - c1);
             const T P2 = (Sb - T(0.5)) * (t2 - X2[a]) - (p2 - Sb * X2[a]) + S * (t2 - c2);
-            const T nd = m.nd[o];
-            zs[(nd > T(0) ? 0 : (size_t)m.nE * L) + (size_t)m.eoc[o] * L + l] =
-                nd * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
+            const T ndo = nd[o];
+            if (act)
+                zs[(ndo > T(0) ? 0 : (size_t)m.nE * L) + (size_t)eoc[o] * L + l] =
+                    ndo * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
         }
     }
-    epilogue_l(i, l, L, -t1 / m.area[i], s0, s1, flag);
+    if (act) epilogue_l(i, l, L, -t1 / m.area[i], s0, s1, flag);
 }
 
 template <typename T>
@@ -603,12 +641,25 @@ hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, co
     return launch(k_edge<T>, dim3(nbe + nba), s, ev0, ev1, zs, nE, lo, hi, nbe, s0, s1, aux, flag);
 }
 
+// The wave-per-element map pays once few lanes of a wave go idle: measured
+// on a 200k-cell mesh it is 8% slower per step than one thread per pair at
+// 48 layers and 8% faster at 64 (24% at 128); the crossover is near 56.
+#ifndef LTS_WAVE_LAYERS_MIN
+#define LTS_WAVE_LAYERS_MIN 56
+#endif
+inline bool wave_layers(int L) { return L >= LTS_WAVE_LAYERS_MIN; }
+inline long layer_threads(int n, int L) {
+    return wave_layers(L) ? (long)n * ((L + 63) / 64) * 64 : (long)n * L;
+}
+
 template <typename T>
 hipError_t launch_vertex_l(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo, int v_hi,
                            int L, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (v_hi <= v_lo) return hipSuccess;
-    return launch(k_vertex_l<T>, dim3(nblocks((long)(v_hi - v_lo) * L)), s, ev0, ev1, m, h, u, q,
-                  v_lo, v_hi, L);
+    const dim3 grid(nblocks(layer_threads(v_hi - v_lo, L)));
+    if (wave_layers(L))
+        return launch(k_vertex_l<T, true>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi, L);
+    return launch(k_vertex_l<T, false>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi, L);
 }
 
 template <typename T>
@@ -616,12 +667,19 @@ hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q
                          int c_lo, int c_hi, int L, T g, const Seg<T>& s0, const Seg<T>& s1,
                          int* flag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (c_hi <= c_lo) return hipSuccess;
-    const dim3 grid(nblocks((long)(c_hi - c_lo) * L));
-    if (padded_slots(m.maxE) == 8)
-        return launch(k_cell_l<T, 8>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,
-                      flag);
-    return launch(k_cell_l<T, 16>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,
-                  flag);
+    const dim3 grid(nblocks(layer_threads(c_hi - c_lo, L)));
+    const bool w = wave_layers(L), g8 = padded_slots(m.maxE) == 8;
+    if (w && g8)
+        return launch(k_cell_l<T, 8, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
+                      s0, s1, flag);
+    if (w)
+        return launch(k_cell_l<T, 16, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
+                      s0, s1, flag);
+    if (g8)
+        return launch(k_cell_l<T, 8, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
+                      s0, s1, flag);
+    return launch(k_cell_l<T, 16, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
+                  s0, s1, flag);
 }
 
 template <typename T>

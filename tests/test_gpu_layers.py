@@ -130,3 +130,32 @@ def test_layers_rhs_and_identical_layers(case):
     assert rel_l2(gh[0], h1, m.areaCell) < 1e-13 and rel_l2(gu[0], u1) < 1e-12
     c.close()
     one.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_many_layers_wave_map(case, prec):
+    """70 layers take the wave-per-cell map of the layered kernels (one full
+    chunk of 64 layers and a ragged chunk of 6).  The three states of the
+    fixture repeat over the layers: every layer matches the oracle run of its
+    state, and layers with the same state agree bit for bit whatever their
+    lane."""
+    m, fm, o, R, hs, us, dt = case
+    nl = 70
+    say("many layers", prec, nl)
+    c = lts.LTSContext(0, prec, layers=nl)
+    c.upload_mesh(m, fm, 2, 2)
+    idx = np.arange(nl) % L
+    c.init_state(hs[idx], us[idx])
+    c.step(dt, 4, 3)
+    gh, gu = c.get_state()
+    tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
+    for k in range(L):
+        rh, ru = o.lts(hs[k], us[k], dt, 4, R, n=3)
+        ls = np.flatnonzero(idx == k)
+        for l in ls:
+            assert np.array_equal(gh[l], gh[ls[0]]) and np.array_equal(gu[l], gu[ls[0]])
+        eh = rel_l2(gh[ls[0]], rh, m.areaCell)
+        eu = rel_l2(gu[ls[0]], ru, m.dvEdge * m.dcEdge)
+        say("state", k, "rel L2 h", eh, "u", eu)
+        assert eh < tol_h and eu < tol_u
+    c.close()

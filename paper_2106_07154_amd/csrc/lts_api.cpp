@@ -334,7 +334,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     if ((s = upload_vec<T>(c, &dm->bot, conv<T>(bot)))) return s;
     c->bot_perm = bot;
     c->area_perm = area;
-    c->pert = sizeof(T) < sizeof(double);
+    c->pert = perturbation_form<T>();
     if (c->pert) {
         void* p = nullptr;
         if ((s = dalloc(c, &p, nC * sizeof(T)))) return s;

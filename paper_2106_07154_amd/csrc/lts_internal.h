@@ -9,6 +9,13 @@
 
 namespace lts {
 
+// Thickness storage form of a precision: FP32 contexts store the perturbation
+// eta = h - href (see DevMesh::href), FP64 contexts h itself.
+template <typename T>
+constexpr bool perturbation_form() {
+    return sizeof(T) < sizeof(double);
+}
+
 // Device mesh, permuted so that every LTS region is a contiguous range.
 // Per-cell slot tables are cell-major with G = padded_slots(maxE) slots per
 // cell ([cell][G]): the cell kernel gives each slot its own lane, so a
@@ -30,6 +37,7 @@ struct DevMesh {
     // beta = b.  Otherwise the state holds eta = h - href (perturbation form,
     // used in FP32) and beta = href + b - H_s, so g(h + b) = g(eta + beta) +
     // const and the constant drops out of every gradient.
+    // href != nullptr exactly when perturbation_form<T>() holds.
     const T* href;         // [nC] or nullptr
     const T* beta;         // [nC]
     const int32_t* eov;    // [3][nV]

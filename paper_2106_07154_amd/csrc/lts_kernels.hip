@@ -80,7 +80,7 @@ __device__ __forceinline__ void epilogue(int j, T G, const Seg<T>& s0, const Seg
 // h_v the kite-weighted thickness.
 template <typename T>
 __device__ __forceinline__ T vertex_q(const DevMesh<T>& m, const T* __restrict__ h,
-                                      const T* __restrict__ u, int v) {
+                                      const T* __restrict__ u, int v, bool hr) {
     const int nV = m.nV;
     T circ = 0, hv = 0;
 #pragma unroll
@@ -88,23 +88,31 @@ __device__ __forceinline__ T vertex_q(const DevMesh<T>& m, const T* __restrict__
         const int o = k * nV + v;
         const int c = m.cov[o];
         circ += m.tdc[o] * u[m.eov[o]];
-        hv += m.kite[o] * (m.href ? m.href[c] + h[c] : h[c]);
+        hv += m.kite[o] * (hr ? m.href[c] + h[c] : h[c]);
     }
     return (m.fA[v] + circ) / hv;
 }
 
-template <typename T>
-__device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __restrict__ h,
-                                            const T* __restrict__ u, T* __restrict__ q, int v) {
-    q[v] = vertex_q(m, h, u, v);
+// Optional operands (the reference thickness href, the vertex PV array q):
+// K = 1 present, K = 0 absent, both known at compile time so the kernel has
+// no branch on them; K = -1 tests the pointer at run time.
+template <int K>
+__device__ __forceinline__ bool present(const void* p) {
+    return K < 0 ? p != nullptr : K != 0;
 }
 
-template <typename T>
+template <typename T, int HR>
+__device__ __forceinline__ void vertex_body(const DevMesh<T>& m, const T* __restrict__ h,
+                                            const T* __restrict__ u, T* __restrict__ q, int v) {
+    q[v] = vertex_q(m, h, u, v, present<HR>(m.href));
+}
+
+template <typename T, int HR>
 __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __restrict__ h,
                                                    const T* __restrict__ u, T* __restrict__ q,
                                                    int v_lo, int v_hi) {
     const int v = v_lo + xcd_block() * kBlock + threadIdx.x;
-    if (v < v_hi) vertex_body(m, h, u, q, v);
+    if (v < v_hi) vertex_body<T, HR>(m, h, u, q, v);
 }
 
 // Cell kernel: one lane per edge slot, G lanes per cell (G = 8 or 16), so a
@@ -174,7 +182,8 @@ __device__ __forceinline__ T gprev(T x, int lane) {
 }
 
 // t: thread index within the cell range (G lanes per cell, groups aligned).
-template <typename T, int G>
+// HR, QP: presence of m.href and q (see present).
+template <typename T, int G, int HR, int QP>
 __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restrict__ h,
                                           const T* __restrict__ u, const T* __restrict__ q,
                                           T* __restrict__ zs, int t, int c_lo, int c_hi, T g,
@@ -184,19 +193,20 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     const bool live = ic < c_hi;
     const int i = live ? ic : c_hi - 1;  // dead lanes shadow a valid cell
     const T* __restrict__ href = m.href;
+    const bool hr = present<HR>(href);
     const size_t o = (size_t)i * G + lane;
     const int e = m.eoc[o];
     const int nb = m.coc[o];
     const int v = m.voc[o];
     const T nl = m.nl[o], kc = m.kc[o], kf = m.kf[o], nd = m.nd[o];
     const int n = m.nEoC[i];
-    const T hi = href ? href[i] + h[i] : h[i];
-    const T hn = href ? href[nb] + h[nb] : h[nb];
+    const T hi = hr ? href[i] + h[i] : h[i];
+    const T hn = hr ? href[nb] + h[nb] : h[nb];
     const T ue = u[e];
     // q == nullptr: no vertex pass ran; each lane evaluates the PV of its own
     // vertex (every vertex is then evaluated by each of its cells, with the
     // same arithmetic as the vertex kernel)
-    const T qv = q ? q[v] : vertex_q(m, h, u, v);
+    const T qv = present<QP>(q) ? q[v] : vertex_q(m, h, u, v, hr);
     const T Ga = nl * (T(0.5) * (hi + hn) * ue);
     const T K = gsum<T, G>(kc * ue * ue);
     const T Sinc = gscan<T, G>(kf, lane);
@@ -215,14 +225,14 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     if (live && lane == 0) epilogue(i, -t1 / m.area[i], s0, s1, flag);
 }
 
-template <typename T, int G>
+template <typename T, int G, int HR, int QP>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
                                                  int* flag) {
-    cell_body<T, G>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g, s0, s1,
-                    flag);
+    cell_body<T, G, HR, QP>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
+                            s0, s1, flag);
 }
 
 template <typename T>
@@ -293,7 +303,7 @@ __global__ __launch_bounds__(512) void kb_vertex(const Item<T>* __restrict__ ite
     for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const Item<T>& w = items[find_item(items, nitems, vb)];
         const int v = w.lo + (vb - w.first) * (int)blockDim.x + threadIdx.x;
-        if (v < w.hi) vertex_body(w.m, w.h, w.u, w.q, v);
+        if (v < w.hi) vertex_body<T, perturbation_form<T>()>(w.m, w.h, w.u, w.q, v);
     }
 }
 
@@ -302,8 +312,9 @@ __global__ __launch_bounds__(512) void kb_cell(const Item<T>* __restrict__ items
                                                int nvb) {
     for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const Item<T>& w = items[find_item(items, nitems, vb)];
-        cell_body<T, G>(w.m, w.h, w.u, w.q, w.zs, (vb - w.first) * (int)blockDim.x + threadIdx.x,
-                        w.lo, w.hi, w.g, w.s0, w.s1, w.flag);
+        cell_body<T, G, perturbation_form<T>(), 1>(w.m, w.h, w.u, w.q, w.zs,
+                               (vb - w.first) * (int)blockDim.x + threadIdx.x, w.lo, w.hi, w.g,
+                               w.s0, w.s1, w.flag);
     }
 }
 
@@ -478,7 +489,7 @@ __device__ __forceinline__ void layer_slot(int n_lo, int L, int& k, int& l, bool
     l = act ? l0 : L - 1;
 }
 
-template <typename T, bool W>
+template <typename T, bool W, int HR>
 __global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __restrict__ h,
                                                      const T* __restrict__ u,
                                                      T* __restrict__ q, int v_lo, int v_hi,
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __re
         const int c = cov[o];
         const T hc = h[(size_t)c * L + l];
         circ += tdc[o] * u[(size_t)eov[o] * L + l];
-        hv += kite[o] * (href ? href[c] + hc : hc);
+        hv += kite[o] * (present<HR>(href) ? href[c] + hc : hc);
     }
     const T qv = (m.fA[v] + circ) / hv;
     if (act) q[(size_t)v * L + l] = qv;
@@ -508,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __re
 
 // The cell's slots in a loop, with the same O(n) prefix-sum form of the PV
 // share as the single-layer cell kernel.
-template <typename T, int G, bool W>
+template <typename T, int G, bool W, int HR>
 __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __restrict__ h,
                                                    const T* __restrict__ u,
                                                    const T* __restrict__ q,
@@ -529,7 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     const T* __restrict__ href = m.href;
     const int n = m.nEoC[i];
     const size_t il = (size_t)i * L + l;
-    const T hi = href ? href[i] + h[il] : h[il];
+    const bool hr = present<HR>(href);
+    const T hi = hr ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
     T qprev = q[(size_t)voc[(size_t)i * G + n - 1] * L + l];
     T X1[G], X2[G], qtA[G];
@@ -541,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
             const int e = eoc[o], nb = coc[o];
             const T ue = u[(size_t)e * L + l];
             const T hn0 = h[(size_t)nb * L + l];
-            const T hn = href ? href[nb] + hn0 : hn0;
+            const T hn = hr ? href[nb] + hn0 : hn0;
             const T qa = q[(size_t)voc[o] * L + l];
             const T qt = T(0.5) * (qprev + qa);
             qprev = qa;
@@ -616,7 +628,9 @@ template <typename T>
 hipError_t launch_vertex(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo, int v_hi,
                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (v_hi <= v_lo) return hipSuccess;
-    return launch(k_vertex<T>, dim3(nblocks(v_hi - v_lo)), s, ev0, ev1, m, h, u, q, v_lo, v_hi);
+    const dim3 grid(nblocks(v_hi - v_lo));
+    if (m.href) return launch(k_vertex<T, 1>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi);
+    return launch(k_vertex<T, 0>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi);
 }
 
 template <typename T>
@@ -626,9 +640,14 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
     if (c_hi <= c_lo) return hipSuccess;
     const int G = padded_slots(m.maxE);
     const dim3 grid(nblocks((long)(c_hi - c_lo) * G));
-    if (G == 8)
-        return launch(k_cell<T, 8>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
-    return launch(k_cell<T, 16>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
+    // instantiations for the two thickness forms with q from the vertex
+    // pass; the fused-PV form (q == nullptr) tests href at run time
+#define LTS_CELL(GG, HR, QP)                                                                     \
+    launch(k_cell<T, GG, HR, QP>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag)
+    if (!q) return G == 8 ? LTS_CELL(8, -1, 0) : LTS_CELL(16, -1, 0);
+    if (m.href) return G == 8 ? LTS_CELL(8, 1, 1) : LTS_CELL(16, 1, 1);
+    return G == 8 ? LTS_CELL(8, 0, 1) : LTS_CELL(16, 0, 1);
+#undef LTS_CELL
 }
 
 template <typename T>
@@ -657,9 +676,11 @@ hipError_t launch_vertex_l(const DevMesh<T>& m, const T* h, const T* u, T* q, in
                            int L, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (v_hi <= v_lo) return hipSuccess;
     const dim3 grid(nblocks(layer_threads(v_hi - v_lo, L)));
-    if (wave_layers(L))
-        return launch(k_vertex_l<T, true>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi, L);
-    return launch(k_vertex_l<T, false>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi, L);
+#define LTS_VERTEX_L(W, HR) \
+    launch(k_vertex_l<T, W, HR>, grid, s, ev0, ev1, m, h, u, q, v_lo, v_hi, L)
+    if (wave_layers(L)) return m.href ? LTS_VERTEX_L(true, 1) : LTS_VERTEX_L(true, 0);
+    return m.href ? LTS_VERTEX_L(false, 1) : LTS_VERTEX_L(false, 0);
+#undef LTS_VERTEX_L
 }
 
 template <typename T>
@@ -669,17 +690,16 @@ hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q
     if (c_hi <= c_lo) return hipSuccess;
     const dim3 grid(nblocks(layer_threads(c_hi - c_lo, L)));
     const bool w = wave_layers(L), g8 = padded_slots(m.maxE) == 8;
-    if (w && g8)
-        return launch(k_cell_l<T, 8, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
-                      s0, s1, flag);
-    if (w)
-        return launch(k_cell_l<T, 16, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
-                      s0, s1, flag);
-    if (g8)
-        return launch(k_cell_l<T, 8, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
-                      s0, s1, flag);
-    return launch(k_cell_l<T, 16, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g,
-                  s0, s1, flag);
+#define LTS_CELL_L(GG, W, HR)                                                                    \
+    launch(k_cell_l<T, GG, W, HR>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,  \
+           flag)
+    if (m.href) {
+        if (w) return g8 ? LTS_CELL_L(8, true, 1) : LTS_CELL_L(16, true, 1);
+        return g8 ? LTS_CELL_L(8, false, 1) : LTS_CELL_L(16, false, 1);
+    }
+    if (w) return g8 ? LTS_CELL_L(8, true, 0) : LTS_CELL_L(16, true, 0);
+    return g8 ? LTS_CELL_L(8, false, 0) : LTS_CELL_L(16, false, 0);
+#undef LTS_CELL_L
 }
 
 template <typename T>

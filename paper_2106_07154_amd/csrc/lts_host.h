@@ -14,13 +14,6 @@ namespace lts {
 
 enum PassKind { P_FULL = 0, P_STEP1, P_STEP2, P_STEP3, P_STEP4, P_N };
 
-// Passes whose cell range is at most this many cells evaluate the vertex PV
-// inside the cell kernel when fuse_q == 1 (small passes are launch-bound, so
-// one launch fewer outweighs each vertex being evaluated by all its cells).
-#ifndef LTS_FUSE_Q_DEFAULT
-#define LTS_FUSE_Q_DEFAULT 0
-#endif
-constexpr int kFuseQCells = 100000;
 
 struct PassPlan {
     int c_lo = 0, c_hi = 0;    // cell kernel range (targets plus cells of target edges)
@@ -85,9 +78,6 @@ struct lts_ctx {
     int g_kind = -1, g_M = 0;
     double g_dt = 0.0;
 
-    // vertex-PV placement: 0 separate vertex kernel, 1 fused into the cell
-    // kernel for passes of at most kFuseQCells cells, 2 always fused
-    int fuse_q = LTS_FUSE_Q_DEFAULT;
 
     // timing
     bool timing = false;
@@ -213,24 +203,14 @@ struct Run {
             done(KC_EDGE, e0, e1, kernel_bytes<T>(P, KC_EDGE, es0, es1, aux, L));
             return LTS_OK;
         }
-        // vertex PV, or evaluated by the cell kernel itself (see fuse_q)
-        const bool fuse = c->fuse_q == 2 || (c->fuse_q == 1 && P.c_hi - P.c_lo <= kFuseQCells);
-        if (!fuse) {
-            if ((st = events(&e0, &e1))) return st;
-            HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
-            done(KC_VERTEX, e0, e1, kernel_bytes<T>(P, KC_VERTEX, cs0, cs1, aux));
-        }
-        // cell tendency + partials
+        // vertex PV, then the cell tendency
         if ((st = events(&e0, &e1))) return st;
-        HIPCHK(c, launch_cell<T>(dm, h, u, fuse ? nullptr : q, zs, P.c_lo, P.c_hi, (T)c->g, cs0,
-                                 cs1, c->flag, s, e0, e1));
-        // fused: the vertex tables are read too, q is neither written nor
-        // read; h and u at the vertices are taken as already counted
-        done(KC_CELL, e0, e1,
-             kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux) +
-                 (fuse ? (P.v_hi - P.v_lo) * (3.0 * 4 * 2 + 7.0 * sizeof(T)) -
-                             P.c_uniq_q * (double)sizeof(T)
-                       : 0.0));
+        HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
+        done(KC_VERTEX, e0, e1, kernel_bytes<T>(P, KC_VERTEX, cs0, cs1, aux));
+        if ((st = events(&e0, &e1))) return st;
+        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag,
+                                 s, e0, e1));
+        done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux));
         // edge tendency (+ appended element-wise job)
         if ((st = events(&e0, &e1))) return st;
         HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1));

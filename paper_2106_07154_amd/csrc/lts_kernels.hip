@@ -141,9 +141,9 @@ __device__ __forceinline__ T vertex_q(const DevMesh<T>& m, const T* __restrict__
     return (m.fA[v] + circ) / hv;
 }
 
-// Optional operands (the reference thickness href, the vertex PV array q):
-// K = 1 present, K = 0 absent, both known at compile time so the kernel has
-// no branch on them; K = -1 tests the pointer at run time.
+// Optional operand (the reference thickness href): K = 1 present, K = 0
+// absent, both known at compile time so the kernel has no branch on it;
+// K = -1 tests the pointer at run time.
 template <int K>
 __device__ __forceinline__ bool present(const void* p) {
     return K < 0 ? p != nullptr : K != 0;
@@ -235,43 +235,62 @@ __device__ __forceinline__ void hold(T& x) {
     asm volatile("" : "+v"(x));
 }
 
-// t: thread index within the cell range (G lanes per cell, groups aligned).
-// HR, QP: presence of m.href and q (see present).  PRE: every load of the
-// kernel is issued up front with the gathers, the epilogue's operands
-// included (epi_loads), instead of after the tendency.
-template <typename T, int G, int HR, int QP, bool PRE>
-__device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restrict__ h,
-                                          const T* __restrict__ u, const T* __restrict__ q,
-                                          T* __restrict__ zs, int t, int c_lo, int c_hi, T g,
-                                          const Seg<T>& s0, const Seg<T>& s1, int* flag) {
-    const int lane = t & (G - 1);
-    const int ic = c_lo + t / G;
-    const bool live = ic < c_hi;
-    const int i = live ? ic : c_hi - 1;  // dead lanes shadow a valid cell
+// One cell lane between its loads and its arithmetic.
+template <typename T>
+struct CellLane {
+    size_t o;  // slot-table entry
+    int i, lane, n, e;
+    bool live;
+    T nl, kc, kf, nd, hi, hn, hc, ue, bi, ai;
+    EpiIn<T> ep;
+};
+
+// Loads of lane `lane` of cell i (a valid cell; live: the lane's own cell is
+// in the pass range).  HR: presence of m.href (see present).  PRE: the
+// epilogue's operands are loaded here too (epi_loads), not after the
+// tendency.
+template <typename T, int G, int HR, bool PRE>
+__device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* __restrict__ h,
+                                                  const T* __restrict__ u, int i, int lane,
+                                                  bool live, const Seg<T>& s0, const Seg<T>& s1) {
+    CellLane<T> c;
     const T* __restrict__ href = m.href;
     const bool hr = present<HR>(href);
-    const size_t o = (size_t)i * G + lane;
-    const int e = m.eoc[o];
-    const int nb = m.coc[o];
-    const int v = m.voc[o];
-    const T nl = m.nl[o], kc = m.kc[o], kf = m.kf[o], nd = m.nd[o];
-    const int n = m.nEoC[i];
-    const T hi = hr ? href[i] + h[i] : h[i];
-    const T hn = hr ? href[nb] + h[nb] : h[nb];
-    const T ue = u[e];
+    c.o = (size_t)i * G + lane;
+    c.i = i;
+    c.lane = lane;
+    c.live = live;
+    c.e = m.eoc[c.o];
+    const int nb = m.coc[c.o];
+    c.nl = m.nl[c.o];
+    c.kc = m.kc[c.o];
+    c.kf = m.kf[c.o];
+    c.nd = m.nd[c.o];
+    c.n = m.nEoC[i];
+    c.hc = h[i];
+    c.hi = hr ? href[i] + c.hc : c.hc;
+    c.hn = hr ? href[nb] + h[nb] : h[nb];
+    c.ue = u[c.e];
     // every lane of the cell reads its epilogue operands (one address per
     // cell); lane 0 applies the epilogue
-    EpiIn<T> ep{};
-    if (PRE) ep = epi_loads(i, s0, s1, h);
-    // q == nullptr: no vertex pass ran; each lane evaluates the PV of its own
-    // vertex (every vertex is then evaluated by each of its cells, with the
-    // same arithmetic as the vertex kernel)
-    const T qv = present<QP>(q) ? q[v] : vertex_q(m, h, u, v, hr);
-    const T Ga = nl * (T(0.5) * (hi + hn) * ue);
-    const T K = gsum<T, G>(kc * ue * ue);
-    const T Sinc = gscan<T, G>(kf, lane);
-    const T Sb = Sinc - kf;                      // S_b: fractions before slot b
-    const T Sn = gsum<T, G>(kf);                 // S_n
+    c.ep = EpiIn<T>{};
+    if (PRE) c.ep = epi_loads(i, s0, s1, h);
+    c.bi = m.beta[i];
+    c.ai = m.area[i];
+    return c;
+}
+
+// Arithmetic of a cell lane given the PV qv of the vertex after its slot.
+template <typename T, int G, bool PRE>
+__device__ __forceinline__ void cell_math(const DevMesh<T>& m, CellLane<T> c, T qv,
+                                          T* __restrict__ zs, T g, const Seg<T>& s0,
+                                          const Seg<T>& s1, int* flag) {
+    const int lane = c.lane;
+    const T Ga = c.nl * (T(0.5) * (c.hi + c.hn) * c.ue);
+    const T K = gsum<T, G>(c.kc * c.ue * c.ue);
+    const T Sinc = gscan<T, G>(c.kf, lane);
+    const T Sb = Sinc - c.kf;                    // S_b: fractions before slot b
+    const T Sn = gsum<T, G>(c.kf);               // S_n
     const T qt = T(0.5) * (gprev<T, G>(qv, lane) + qv);
     const T X1 = Ga, X2 = Ga * qt;
     const T c1 = gscan<T, G>(X1, lane), c2 = gscan<T, G>(X2, lane);
@@ -279,35 +298,49 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     const T p1 = gsum<T, G>(Sb * X1), p2 = gsum<T, G>(Sb * X2);
     const T P1 = (Sb - T(0.5)) * (t1 - X1) - (p1 - Sb * X1) + Sn * (t1 - c1);
     const T P2 = (Sb - T(0.5)) * (t2 - X2) - (p2 - Sb * X2) + Sn * (t2 - c2);
-    T bi = m.beta[i], ai = m.area[i], ndo = nd;
     if (PRE) {
         // Uses outside the conditional stores below keep these loads with
-        // the table loads at the top; sunk into the stores, each would add
-        // a dependent memory round trip.
-        hold(bi);
-        hold(ai);
-        hold(ndo);
-        hold(ep.xo);
-        hold(ep.xc);
-        hold(ep.ac);
+        // the others at the top; sunk into the stores, each would add a
+        // dependent memory round trip.
+        hold(c.bi);
+        hold(c.ai);
+        hold(c.nd);
+        hold(c.ep.xo);
+        hold(c.ep.xc);
+        hold(c.ep.ac);
     }
-    const T phi = g * (h[i] + bi) + K;
-    if (live && lane < n)
-        zs[(ndo > T(0) ? 0 : (size_t)m.nE) + e] = ndo * (phi + T(0.5) * qt * P1 + T(0.5) * P2);
-    if (live && lane == 0) {
-        if (PRE) epilogue(i, -t1 / ai, s0, s1, ep, flag);
-        else epilogue(i, -t1 / ai, s0, s1, flag);
+    const T phi = g * (c.hc + c.bi) + K;
+    if (c.live && lane < c.n)
+        zs[(c.nd > T(0) ? 0 : (size_t)m.nE) + c.e] =
+            c.nd * (phi + T(0.5) * qt * P1 + T(0.5) * P2);
+    if (c.live && lane == 0) {
+        if (PRE) epilogue(c.i, -t1 / c.ai, s0, s1, c.ep, flag);
+        else epilogue(c.i, -t1 / c.ai, s0, s1, flag);
     }
 }
 
-template <typename T, int G, int HR, int QP>
+// Cell lanes reading q from the vertex pass.  t: thread index within the
+// cell range (G lanes per cell, groups aligned).
+template <typename T, int G, int HR, bool PRE>
+__device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restrict__ h,
+                                          const T* __restrict__ u, const T* __restrict__ q,
+                                          T* __restrict__ zs, int t, int c_lo, int c_hi, T g,
+                                          const Seg<T>& s0, const Seg<T>& s1, int* flag) {
+    const int ic = c_lo + t / G;
+    const bool live = ic < c_hi;
+    const int i = live ? ic : c_hi - 1;  // dead lanes shadow a valid cell
+    const CellLane<T> c = cell_loads<T, G, HR, PRE>(m, h, u, i, t & (G - 1), live, s0, s1);
+    cell_math<T, G, PRE>(m, c, q[m.voc[c.o]], zs, g, s0, s1, flag);
+}
+
+template <typename T, int G, int HR>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
                                                  int* flag) {
-    cell_body<T, G, HR, QP, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
-                            s0, s1, flag);
+    cell_body<T, G, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
+                              s0, s1, flag);
 }
 
 template <typename T>
@@ -390,7 +423,7 @@ __global__ __launch_bounds__(512) void kb_cell(const Item<T>* __restrict__ items
                                                int nvb) {
     for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const Item<T>& w = items[find_item(items, nitems, vb)];
-        cell_body<T, G, perturbation_form<T>(), 1, false>(w.m, w.h, w.u, w.q, w.zs,
+        cell_body<T, G, perturbation_form<T>(), false>(w.m, w.h, w.u, w.q, w.zs,
                                (vb - w.first) * (int)blockDim.x + threadIdx.x, w.lo, w.hi, w.g,
                                w.s0, w.s1, w.flag);
     }
@@ -718,13 +751,10 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
     if (c_hi <= c_lo) return hipSuccess;
     const int G = padded_slots(m.maxE);
     const dim3 grid(nblocks((long)(c_hi - c_lo) * G));
-    // instantiations for the two thickness forms with q from the vertex
-    // pass; the fused-PV form (q == nullptr) tests href at run time
-#define LTS_CELL(GG, HR, QP)                                                                     \
-    launch(k_cell<T, GG, HR, QP>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag)
-    if (!q) return G == 8 ? LTS_CELL(8, -1, 0) : LTS_CELL(16, -1, 0);
-    if (m.href) return G == 8 ? LTS_CELL(8, 1, 1) : LTS_CELL(16, 1, 1);
-    return G == 8 ? LTS_CELL(8, 0, 1) : LTS_CELL(16, 0, 1);
+#define LTS_CELL(GG, HR) \
+    launch(k_cell<T, GG, HR>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag)
+    if (m.href) return G == 8 ? LTS_CELL(8, 1) : LTS_CELL(16, 1);
+    return G == 8 ? LTS_CELL(8, 0) : LTS_CELL(16, 0);
 #undef LTS_CELL
 }
 

@@ -532,17 +532,19 @@ def bench_surrogate(args):
         runs[f"lts3_dt_x{kk}"] = {"ms": round(ms, 3), "err": err(h)}
         c.close()
         log(f"LTS3 dt x{kk}: {ms:.2f} ms, err {runs[f'lts3_dt_x{kk}']['err']:.3e}")
-    # global FP64 SSPRK3 at the fine step dt/M times a factor (whole step
-    # counts over the same horizon; above the stability limit the run fails)
+    # global FP64 SSPRK3 at about the fine step dt/M times a factor: a whole
+    # number of steps over the same horizon K dt (the step is the horizon over
+    # the count); above the stability limit the run fails
     for f in (1.0, 1.25, 1.6, 2.0, 2.5):
         n_rk = int(round(K * M / f))
+        dt_rk = K * dt / n_rk
         c = make("fp64", ev)
         try:
-            c.step_rk3(f * dt / M, 1)
+            c.step_rk3(dt_rk, 1)
             c.init_state(*init(ev))
-            ms = timed(torch, stream, lambda: c.step_rk3(f * dt / M, n_rk))
+            ms = timed(torch, stream, lambda: c.step_rk3(dt_rk, n_rk))
             h, _ = c.get_state()
-            runs[f"rk3_fine_dt_x{f:g}"] = {"ms": round(ms, 3), "err": err(h)}
+            runs[f"rk3_fine_dt_x{f:g}"] = {"ms": round(ms, 3), "err": err(h), "steps": n_rk}
         except lts.LTSError as ex:
             runs[f"rk3_fine_dt_x{f:g}"] = {"ms": None, "err": float("inf"), "diverged": str(ex)}
         c.close()

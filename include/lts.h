@@ -55,8 +55,9 @@ typedef enum { LTS_FP64 = 0, LTS_FP32 = 1 } lts_precision;
 /* Region labels, eq:indexSetsCells / eq:indexSetsEdges. */
 typedef enum { LTS_C = 0, LTS_I2 = 1, LTS_I1 = 2, LTS_F = 3 } lts_region;
 
-/* Largest number of edges a cell may have. */
-#define LTS_MAX_EDGES 10
+/* Largest number of edges a cell may have: the slot capacity of the cell
+   kernels (8 lanes per cell up to 8 edges, 16 lanes above). */
+#define LTS_MAX_EDGES 16
 
 typedef struct lts_ctx lts_ctx;
 

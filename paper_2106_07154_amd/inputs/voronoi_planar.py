@@ -279,6 +279,25 @@ def jittered_hex_points(nx, ny, dc, jitter, seed):
     return p, Lx, Ly
 
 
+def ring_hex_points(nx, ny, dc, n_ring, r_ring, iters):
+    """A hex lattice whose points within 1.9 dc of the domain centre are
+    replaced by the centre and a regular ring of n_ring points at radius
+    r_ring dc, both held in place while the other points take `iters`
+    uniform Lloyd steps: the Voronoi mesh has one n_ring-sided cell (up to
+    11 with n_ring = 11, r_ring = 1.2, iters = 20) among mostly hexagons."""
+    p, Lx, Ly = jittered_hex_points(nx, ny, dc, 0.0, seed=0)
+    c = np.array([Lx / 2, Ly / 2])
+    keep = np.hypot(*(p - c).T) > 1.9 * dc
+    ang = 2.0 * math.pi * np.arange(n_ring) / n_ring
+    ring = c + r_ring * dc * np.stack([np.cos(ang), np.sin(ang)], 1)
+    pts = np.concatenate([c[None], ring, p[keep]])
+    pinned = pts[:1 + n_ring].copy()
+    for _ in range(iters):
+        pts = lloyd_step(pts, Lx, Ly, lambda x, y: np.ones_like(x))
+        pts[:1 + n_ring] = pinned
+    return pts, Lx, Ly
+
+
 # ---------------------------------------------------------------------------
 # The variable-resolution planar workload
 

@@ -47,6 +47,22 @@ def irregular():
 
 
 @pytest.fixture(scope="session")
+def ring_mesh():
+    """Periodic Voronoi mesh with one 11-sided cell (a pinned ring of 11
+    generators around the domain centre) among hexagons, pentagons and
+    heptagons, random topography: cells above 8 edges take the 16-lane
+    slot tables of the cell kernels."""
+    from paper_2106_07154_amd.inputs.voronoi_planar import (
+        periodic_voronoi_mesh, ring_hex_points)
+    p, Lx, Ly = ring_hex_points(16, 16, 1.0e4, 11, 1.2, 20)
+    m = periodic_voronoi_mesh(p, Lx, Ly, f0=1.0e-4, name="ring11")
+    rng = np.random.default_rng(13)
+    m.bottom = 20.0 * rng.standard_normal(m.nCells)
+    m.fVertex = 1.0e-4 + 2.0e-5 * rng.standard_normal(m.nVertices)
+    return m
+
+
+@pytest.fixture(scope="session")
 def lloyd_mesh():
     """Small variable-resolution periodic mesh from the Lloyd generator."""
     from paper_2106_07154_amd.inputs.voronoi_planar import (

@@ -145,6 +145,15 @@ def test_rejects_broken_meshes(lib, hex8):
     with pytest.raises(lts.LTSError) as ei:
         lts.plan(m, fm)
     assert ei.value.status == lts.LTS_EMESH
+    # slot tables wider than the cell kernels' 16 lanes
+    m = hex8.copy()
+    for name in ("edgesOnCell", "cellsOnCell", "verticesOnCell"):
+        a = getattr(m, name)
+        setattr(m, name, np.pad(a, ((0, 0), (0, 17 - a.shape[1])), constant_values=-1))
+    m.maxEdges = 17
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm)
+    assert ei.value.status == lts.LTS_EMESH and "LTS_MAX_EDGES" in str(ei.value)
     for bad in (np.zeros(hex8.nCells, np.uint8), np.ones(hex8.nCells, np.uint8)):
         with pytest.raises(lts.LTSError) as ei:
             lts.plan(hex8, bad)

@@ -55,6 +55,15 @@ def test_voronoi_invariants_irregular(irregular):
     _voronoi_invariants(irregular)
 
 
+def test_voronoi_invariants_ring(ring_mesh):
+    """The pinned ring gives exactly one 11-sided cell, at the domain centre."""
+    n = ring_mesh.nEdgesOnCell
+    assert n.max() == 11 and (n == 11).sum() == 1 and (n > 8).sum() == 1
+    i = int(np.argmax(n))
+    assert abs(ring_mesh.xCell[i] - ring_mesh.Lx / 2) < 1e-6
+    _voronoi_invariants(ring_mesh)
+
+
 def test_voronoi_invariants_lloyd(lloyd_mesh):
     _voronoi_invariants(lloyd_mesh)
     # variable resolution: small cells near the centre, large outside

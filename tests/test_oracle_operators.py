@@ -38,7 +38,7 @@ def test_weights_regular_hex_pattern(hex16):
                                    sorted([1 / 3, 1 / 6, 0.0, 1 / 6, 1 / 3] * 2), atol=1e-15)
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "ring_mesh", "lloyd_mesh", "sphere_mesh"])
 def test_weights_antisymmetric(meshname, request):
     """w_{e,e'} = -w_{e',e}: the property behind energy conservation."""
     m = request.getfixturevalue(meshname)
@@ -97,7 +97,7 @@ def test_gradient_of_linear_height(hex16):
     np.testing.assert_allclose(du[ok], -G * (m.normalEdge[ok] @ a), rtol=1e-10, atol=1e-16)
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "ring_mesh"])
 def test_vorticity_of_linear_field(meshname, request):
     """Circulation over the dual triangle is exact for linear fields (Stokes with
     the midpoint rule): zeta_v = dV/dx - dU/dy."""
@@ -115,7 +115,7 @@ def test_vorticity_of_linear_field(meshname, request):
 
 
 # ---------------------------------------------------------------- invariants
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "ring_mesh", "lloyd_mesh", "sphere_mesh"])
 def test_lake_at_rest(meshname, request):
     m = request.getfixturevalue(meshname).copy()
     rng = np.random.default_rng(4)
@@ -126,7 +126,7 @@ def test_lake_at_rest(meshname, request):
     assert np.abs(du).max() < 1e-12 * G * 1000.0 / m.dcEdge.min()
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "lloyd_mesh", "sphere_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "ring_mesh", "lloyd_mesh", "sphere_mesh"])
 def test_energy_and_mass_identities(meshname, request):
     """sum_i A_i (K_i + g(h_i+b_i)) H_i + sum_e l_e d_e h_e u_e U_e = 0 and
     sum_i A_i H_i = 0 for any state: the semi-discrete system conserves energy
@@ -234,7 +234,7 @@ def test_igw_second_order_in_space_and_polarisation():
     assert errs[-1][0] < 0.01 and errs[-1][1] < 0.01
 
 
-@pytest.mark.parametrize("meshname", ["hex16", "irregular", "sphere_mesh"])
+@pytest.mark.parametrize("meshname", ["hex16", "irregular", "ring_mesh", "sphere_mesh"])
 def test_diagnostic_energy_is_conserved_by_rhs(meshname, request):
     """The diagnostic total energy sum_i A_i (h_i K_i + g(h_i^2/2 + h_i b_i)) is
     the invariant of the semi-discrete system: its derivative along R(x),

@@ -45,19 +45,21 @@ def rel_l2(a, b, w):
 KERNEL_SOURCES = ["paper_2106_07154_amd/csrc/lts_kernels.hip",
                   "paper_2106_07154_amd/csrc/lts_internal.h",
                   "paper_2106_07154_amd/csrc/lts_host.h"]
+NN_SOURCES = ["paper_2106_07154_amd/csrc/lts_mpnn.hip",
+              "paper_2106_07154_amd/csrc/lts_mpnn.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, sources=KERNEL_SOURCES):
     """HBM bytes per launch of `kernel` from the recorded FETCH_SIZE + WRITE_SIZE
     counter runs (scaled by the copy calibration), or None when none was
     recorded for this workload or the kernel sources changed since."""
@@ -67,7 +69,7 @@ def measured_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(sources):
         return None
     return ent["bytes_per_launch"]
 
@@ -88,7 +90,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["vr", "igw", "sphere", "ensemble", "surrogate"],
+    ap.add_argument("--workload",
+                    choices=["vr", "igw", "sphere", "ensemble", "surrogate", "gemm"],
                     default="vr")
     ap.add_argument("--layers", type=int, default=1,
                     help="independent layers on the mesh (vertical batching; the layer-l state "
@@ -101,6 +104,8 @@ def main():
     ap.add_argument("--traj-steps", type=int, default=200, help="surrogate: steps per trajectory")
     ap.add_argument("--epochs", type=int, default=20, help="surrogate: training epochs")
     ap.add_argument("--members", type=int, default=64, help="ensemble members")
+    ap.add_argument("--rows", type=int, default=61419,
+                    help="gemm: rows N (default: the surrogate's node count on vr-planar-200k)")
     ap.add_argument("--lloyd", type=int, default=10,
                     help="minimum Lloyd iterations per ensemble member")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -130,6 +135,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "gemm":
+        return bench_gemm(args)
     import numpy as np
     import torch
     from paper_2106_07154_amd.build import LIB
@@ -432,6 +439,80 @@ def bench_ensemble(args):
     ens.close()
     print(json.dumps(out), flush=True)
 
+
+
+def bench_gemm(args):
+    """The surrogate's layer product on the matrix cores alone: relu(A W + b)
+    with A [N x K] and W [K x 64] BF16, FP32 accumulate, BF16 output, for the
+    input layer (K = 16) and the message-passing layers (K = 128), each
+    launched `steps` times back to back on one stream after `warmup`
+    launches and timed with events around the launches."""
+    import numpy as np
+    import torch
+    from paper_2106_07154_amd import lts
+    N = args.rows
+    gen = torch.Generator(device="cpu").manual_seed(2106)
+    stream = torch.cuda.Stream()
+    res = {}
+    for K in (16, 128):
+        A32 = torch.randn(N, K, generator=gen)
+        W32 = torch.randn(K, 64, generator=gen) / math.sqrt(K)
+        b = (0.1 * torch.randn(64, generator=gen)).cuda()
+        bits = lambda x: x.to(torch.bfloat16).view(torch.int16).contiguous().cuda()
+        A, W = bits(A32), bits(W32)
+        Y = torch.empty(N, 64, dtype=torch.int16, device="cuda")
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                lts.nn_gemm_bf16_device(A, W, Y_bf16=Y, bias=b, stream=stream)
+        ms = timed(torch, stream, lambda: [lts.nn_gemm_bf16_device(A, W, Y_bf16=Y, bias=b,
+                                                                   stream=stream)
+                                           for _ in range(args.steps)]) / args.steps
+        flops = 2.0 * N * K * 64
+        nbytes = 2.0 * N * K + 2.0 * K * 64 + 4.0 * 64 + 2.0 * N * 64  # A, W, bias, Y
+        # spot check against the FP32 product of the same BF16 values
+        rows = np.random.default_rng(K).choice(N, 64, replace=False)
+        Ab = A.view(torch.bfloat16).float().cpu().numpy()[rows]
+        Wb = W.view(torch.bfloat16).float().cpu().numpy()
+        ref = np.maximum(Ab @ Wb + b.cpu().numpy(), 0.0)
+        got = Y.view(torch.bfloat16).float().cpu().numpy()[rows]
+        err = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30))
+        res[K] = {"us": round(ms * 1e3, 3), "TFLOP/s": round(flops / ms / 1e9, 2),
+                  "GB/s": round(nbytes / ms / 1e6, 1), "flop_per_byte": round(flops / nbytes, 1),
+                  "bytes_per_launch": int(nbytes), "max_rel_err_sample": err}
+        log(f"gemm N={N} K={K}: {res[K]}")
+    k = res[128]
+    # the oracle's layer product (FP64 numpy, one BLAS thread) on a row
+    # sample, scaled to N rows
+    from threadpoolctl import threadpool_limits
+    from oracle import mpnn as omp
+    rng = np.random.default_rng(5)
+    n_s = min(N, 20000)
+    A64 = rng.standard_normal((n_s, 128))
+    W64 = rng.standard_normal((128, 64)) / math.sqrt(128)
+    b64 = 0.1 * rng.standard_normal(64)
+    with threadpool_limits(limits=1):
+        reps, t0 = 0, time.time()
+        while time.time() - t0 < min(args.cpu_seconds, 10.0) or reps == 0:
+            omp.relu(A64 @ W64 + b64)
+            reps += 1
+        cpu_s = (time.time() - t0) / reps * N / n_s
+    out = {"metric": "BF16 MFMA layer product relu(A W + b) of the surrogate, N x 128 by 128 x 64",
+           "value": k["TFLOP/s"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(k["us"] / 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic", "config": {"workload": f"gemm-{N}x128x64", "rows": N},
+           "roofline": {"bound": "hbm", "achieved": k["GB/s"], "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(k["GB/s"] / 8000.0, 4),
+                        "traffic": measured_traffic("k_gemm<128>", f"gemm-{N}x128x64", NN_SOURCES),
+                        "kernel": "k_gemm", "avg_us": k["us"],
+                        "bytes_per_launch": k["bytes_per_launch"],
+                        "mfma_TFLOP/s": k["TFLOP/s"], "mfma_peak_TFLOP/s": 2500.0},
+           "shapes": {str(K): v for K, v in res.items()},
+           "cpu_baseline": {"value": round(2.0 * N * 128 * 64 / cpu_s / 1e12, 4),
+                            "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+                            "sample": f"the oracle's FP64 layer product on {n_s} rows "
+                                      f"x {reps} repetitions, scaled to {N} rows"}}
+    print(json.dumps(out), flush=True)
 
 
 def bench_surrogate(args):

@@ -133,6 +133,20 @@ lts_status lts_nn_gemm_bf16(int device, const uint16_t *A, int N, int K, const u
 lts_status lts_nn_gemm_tn_bf16(int device, const uint16_t *A, int N, int K, const uint16_t *D,
                                float *P);
 
+/* The forward product on device buffers, enqueued on `stream` (a hipStream_t;
+   NULL: the null stream) without synchronising, for callers that hold device
+   memory and for timing the kernel alone: A [N x K] BF16 (K = 16, 32, ...,
+   128), W [K x 64] BF16, bias [64] FP32 or NULL; Y_f32 [N x 64] receives
+   A W + bias in FP32 and Y_bf16 [N x 64] relu(A W + bias) in BF16, as the
+   network's layers store it; either output may be NULL, not both.  All
+   pointers are device pointers owned by the caller; N = 0 reads and writes
+   nothing (the pointers may then be NULL).  Alignment: A, W, bias and
+   Y_f32 16 bytes, Y_bf16 8 bytes.  LTS_EINVAL for bad sizes, missing or
+   misaligned operands, LTS_EDEVICE if the launch fails. */
+lts_status lts_nn_gemm_bf16_device(const uint16_t *A, int N, int K, const uint16_t *W,
+                                   const float *bias, float *Y_f32, uint16_t *Y_bf16,
+                                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

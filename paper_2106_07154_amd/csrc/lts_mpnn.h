@@ -19,7 +19,8 @@ constexpr int kRawFeat = 9;  // used input columns: 5 physical + 4 region one-ho
 
 // Y = act(A W + bias): A [N x K] BF16 stride lda (K % 16 == 0, K <= 128),
 // W [K x 64] BF16; out_bf (stride ldo, relu if relu != 0) and/or out_f
-// ([N x 64] FP32, no activation).
+// ([N x 64] FP32, no activation).  Alignment: A, W, bias and out_f 16 bytes
+// (lda a multiple of 8), out_bf 8 bytes (ldo a multiple of 4).
 void gemm(const uint16_t* A, int lda, int N, int K, const uint16_t* W, const float* bias,
           int relu, uint16_t* out_bf, int ldo, float* out_f, hipStream_t s);
 

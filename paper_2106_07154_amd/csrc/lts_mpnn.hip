@@ -42,41 +42,134 @@ __device__ __forceinline__ f4 mfma(sh4 a, sh4 b, f4 c) {
 
 inline unsigned nblk(long n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// Y[N x 64] = act(A[N x K] W[K x 64] + bias).  4 waves x 16 rows per block;
-// W staged in LDS.
+// Y[N x 64] = act(A[N x K] W[K x 64] + bias).  4 waves per block, each on
+// kGemmTiles tiles of 16 rows (the W staging below is shared by them).
+// Each tile is computed as the transposed product D^T = W^T A^T (16 columns
+// x 16 rows per MFMA, 4 column tiles), so a lane ends with 4 consecutive
+// columns of one row and stores them with one 16-byte (FP32) or 8-byte
+// (BF16) store.  The reduction index is permuted, identically in both
+// operands (the sum is unchanged): at k-step t the lanes of group
+// g = l / 16 take k = g K/4 + 4 t + j, so a lane's A operands over all steps
+// are one contiguous run of K/4 elements of its row and its W operands one
+// contiguous run of a row of W^T, staged in LDS.  A lane loads its whole A
+// run (16-byte pieces, 8-byte for K = 16) before the W staging, so the two
+// memory round trips overlap.
+constexpr int kGemmTiles = 2;                   // row tiles per wave
+constexpr int kGemmRows = 4 * 16 * kGemmTiles;  // rows per block
+constexpr int kWtStride = 128 + 8;  // LDS row of W^T (padded, 16-byte multiple: 272 B)
+
+__device__ __forceinline__ sh4 bf4(uint32_t x, uint32_t y) {
+    return sh4{(short)(x & 0xFFFFu), (short)(x >> 16), (short)(y & 0xFFFFu), (short)(y >> 16)};
+}
+
+template <int K>
 __global__ __launch_bounds__(256) void k_gemm(const uint16_t* __restrict__ A, int lda, int N,
-                                              int K, const uint16_t* __restrict__ W,
+                                              const uint16_t* __restrict__ W,
                                               const float* __restrict__ bias, int relu,
                                               uint16_t* __restrict__ out_bf, int ldo,
                                               float* __restrict__ out_f) {
-    __shared__ uint16_t Ws[128 * 64];
-    for (int i = threadIdx.x; i < K * 64; i += 256) Ws[i] = W[i];
-    __syncthreads();
+    static_assert(K % 16 == 0 && K <= 128, "K: a multiple of 16 up to 128");
+    constexpr int kl = K / 4;                 // run length per lane group
+    constexpr bool wide = kl % 8 == 0;        // 16-byte pieces
+    constexpr int np = wide ? kl / 8 : kl / 4;  // pieces per run
+    __shared__ uint16_t Wt[64 * kWtStride];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = (blockIdx.x * 4 + wave) * 16;
-    const int r = row0 + (lane & 15);
-    const int kq = 4 * (lane >> 4);
-    f4 acc[4];
-    for (int c = 0; c < 4; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        sh4 a;
-        for (int j = 0; j < 4; ++j)
-            a[j] = r < N ? (short)A[(size_t)r * lda + k0 + kq + j] : (short)0;
-        for (int c = 0; c < 4; ++c) {
-            sh4 b;
-            for (int j = 0; j < 4; ++j) b[j] = (short)Ws[(k0 + kq + j) * 64 + c * 16 + (lane & 15)];
-            acc[c] = mfma(a, b, acc[c]);
+    const int kb = (lane >> 4) * kl;  // start of this lane's run
+    // loads first, in the order they are needed: this thread's share of W
+    // ([K x 64] in 8-column chunks of 16 bytes; chunk i is row i % K, so the
+    // lanes of a wave write consecutive k of one W^T row below, free of LDS
+    // bank conflicts), its A run, the bias of its columns
+    constexpr int nw = (K * 8 + 255) / 256;  // chunks per thread
+    uint4 wq[nw];
+#pragma unroll
+    for (int m = 0; m < nw; ++m) {
+        const int i = threadIdx.x + 256 * m;  // blockDim.x == 256
+        wq[m] = (K * 8 % 256 == 0 || i < K * 8)
+                    ? *reinterpret_cast<const uint4*>(W + (size_t)(i % K) * 64 + (i / K) * 8)
+                    : uint4{0u, 0u, 0u, 0u};
+    }
+    int rows[kGemmTiles];
+    uint4 av[kGemmTiles][np];
+#pragma unroll
+    for (int q = 0; q < kGemmTiles; ++q) {
+        rows[q] = (blockIdx.x * 4 * kGemmTiles + wave * kGemmTiles + q) * 16 + (lane & 15);
+        const uint16_t* ar = A + (size_t)(rows[q] < N ? rows[q] : 0) * lda + kb;
+#pragma unroll
+        for (int p = 0; p < np; ++p) {
+            if (rows[q] >= N) {
+                av[q][p] = uint4{0u, 0u, 0u, 0u};
+            } else if (wide) {
+                av[q][p] = *reinterpret_cast<const uint4*>(ar + 8 * p);
+            } else {
+                const uint2 v = *reinterpret_cast<const uint2*>(ar + 4 * p);
+                av[q][p] = uint4{v.x, v.y, 0u, 0u};
+            }
         }
     }
-    for (int c = 0; c < 4; ++c) {
-        const int col = c * 16 + (lane & 15);
-        const float bb = bias ? bias[col] : 0.f;
+    float4 bq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        bq[c] = bias ? *reinterpret_cast<const float4*>(bias + c * 16 + 4 * (lane >> 4))
+                     : float4{0.f, 0.f, 0.f, 0.f};
+    // W written transposed into LDS
+#pragma unroll
+    for (int m = 0; m < nw; ++m) {
+        const int i = threadIdx.x + 256 * m;
+        if (K * 8 % 256 != 0 && i >= K * 8) break;
+        const int k = i % K, c0 = (i / K) * 8;
+        const uint32_t qw[4] = {wq[m].x, wq[m].y, wq[m].z, wq[m].w};
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int row = row0 + kq + j;
-            if (row >= N) continue;
-            const float v = acc[c][j] + bb;
-            if (out_f) out_f[(size_t)row * 64 + col] = v;
-            if (out_bf) out_bf[(size_t)row * ldo + col] = f2bf(relu ? fmaxf(v, 0.f) : v);
+            Wt[(c0 + 2 * j) * kWtStride + k] = (uint16_t)(qw[j] & 0xFFFFu);
+            Wt[(c0 + 2 * j + 1) * kWtStride + k] = (uint16_t)(qw[j] >> 16);
+        }
+    }
+    __syncthreads();
+    const uint16_t* __restrict__ wr = Wt + (lane & 15) * kWtStride + kb;
+    f4 acc[kGemmTiles][4];
+#pragma unroll
+    for (int q = 0; q < kGemmTiles; ++q)
+        for (int c = 0; c < 4; ++c) acc[q][c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < np; ++p) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (wide) {
+                const uint4 wv = *reinterpret_cast<const uint4*>(wr + c * 16 * kWtStride + 8 * p);
+#pragma unroll
+                for (int q = 0; q < kGemmTiles; ++q) {
+                    acc[q][c] = mfma(bf4(wv.x, wv.y), bf4(av[q][p].x, av[q][p].y), acc[q][c]);
+                    acc[q][c] = mfma(bf4(wv.z, wv.w), bf4(av[q][p].z, av[q][p].w), acc[q][c]);
+                }
+            } else {
+                const uint2 wv = *reinterpret_cast<const uint2*>(wr + c * 16 * kWtStride + 4 * p);
+#pragma unroll
+                for (int q = 0; q < kGemmTiles; ++q)
+                    acc[q][c] = mfma(bf4(wv.x, wv.y), bf4(av[q][p].x, av[q][p].y), acc[q][c]);
+            }
+        }
+    }
+    // lane holds Y[row][16 c + 4 (l / 16) + j], j = 0..3, of each tile
+#pragma unroll
+    for (int q = 0; q < kGemmTiles; ++q) {
+        const int row = rows[q];
+        if (row >= N) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = c * 16 + 4 * (lane >> 4);
+            const float v[4] = {acc[q][c][0] + bq[c].x, acc[q][c][1] + bq[c].y,
+                                acc[q][c][2] + bq[c].z, acc[q][c][3] + bq[c].w};
+            if (out_f)
+                *reinterpret_cast<float4*>(out_f + (size_t)row * 64 + col) =
+                    float4{v[0], v[1], v[2], v[3]};
+            if (out_bf) {
+                uint16_t o[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = f2bf(relu ? fmaxf(v[j], 0.f) : v[j]);
+                *reinterpret_cast<uint2*>(out_bf + (size_t)row * ldo + col) =
+                    uint2{(uint32_t)o[0] | ((uint32_t)o[1] << 16),
+                          (uint32_t)o[2] | ((uint32_t)o[3] << 16)};
+            }
         }
     }
 }
@@ -569,8 +662,18 @@ __global__ void k_gate_final(const double* __restrict__ part, int nparts, double
 void gemm(const uint16_t* A, int lda, int N, int K, const uint16_t* W, const float* bias,
           int relu, uint16_t* out_bf, int ldo, float* out_f, hipStream_t s) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_gemm, dim3(nblk(N, 64)), dim3(256), 0, s, A, lda, N, K, W, bias, relu,
-                       out_bf, ldo, out_f);
+    const dim3 g(nblk(N, kGemmRows)), b(256);
+    switch (K) {
+        case 16: hipLaunchKernelGGL(k_gemm<16>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 32: hipLaunchKernelGGL(k_gemm<32>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 48: hipLaunchKernelGGL(k_gemm<48>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 64: hipLaunchKernelGGL(k_gemm<64>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 80: hipLaunchKernelGGL(k_gemm<80>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 96: hipLaunchKernelGGL(k_gemm<96>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 112: hipLaunchKernelGGL(k_gemm<112>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        case 128: hipLaunchKernelGGL(k_gemm<128>, g, b, 0, s, A, lda, N, W, bias, relu, out_bf, ldo, out_f); break;
+        default: break;  // callers pass K % 16 == 0, K <= 128
+    }
 }
 
 int gemm_tn_parts(int N, int rows_per_block) { return (int)nblk(N, rows_per_block); }

@@ -713,4 +713,19 @@ lts_status lts_nn_gemm_tn_bf16(int device, const uint16_t* A, int N, int K, cons
     return st;
 }
 
+lts_status lts_nn_gemm_bf16_device(const uint16_t* A, int N, int K, const uint16_t* W,
+                                   const float* bias, float* Y_f32, uint16_t* Y_bf16,
+                                   void* stream) {
+    if (N < 0 || K < 16 || K > 128 || K % 16) return LTS_EINVAL;
+    if (N == 0) return LTS_OK;
+    if (!A || !W || (!Y_f32 && !Y_bf16)) return LTS_EINVAL;
+    // the kernel reads W, A and the bias in 16-byte pieces and writes Y_f32
+    // in 16-byte and Y_bf16 in 8-byte pieces
+    auto mis = [](const void* p, uintptr_t a) { return p && (uintptr_t)p % a != 0; };
+    if (mis(W, 16) || mis(A, 16) || mis(bias, 16) || mis(Y_f32, 16) || mis(Y_bf16, 8))
+        return LTS_EINVAL;
+    nn::gemm(A, K, N, K, W, bias, 1, Y_bf16, 64, Y_f32, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? LTS_OK : LTS_EDEVICE;
+}
+
 }  // extern "C"

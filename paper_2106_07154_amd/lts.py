@@ -32,7 +32,7 @@ EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_get_regions"
             "lts_sur_normalize", "lts_sur_set_norm", "lts_sur_get_norm", "lts_sur_get_params",
             "lts_sur_set_params", "lts_sur_train", "lts_sur_grad", "lts_sur_features",
             "lts_sur_predict", "lts_sur_step", "lts_sur_last_error", "lts_sur_destroy",
-            "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16"]
+            "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16", "lts_nn_gemm_bf16_device"]
 
 
 class LTSError(RuntimeError):
@@ -545,6 +545,31 @@ def nn_gemm_bf16(A_bits, W_bits, bias=None, device: int = 0):
     if st != LTS_OK:
         raise LTSError(st, "lts_nn_gemm_bf16")
     return Y
+
+
+def nn_gemm_bf16_device(A, W, Y_f32=None, Y_bf16=None, bias=None, stream=None):
+    """The forward product on torch device tensors (no copies, no sync):
+    A [N x K] and W [K x 64] int16/uint16 BF16 bit patterns, optional FP32
+    bias [64]; fills Y_f32 [N x 64] float32 and/or Y_bf16 [N x 64] (relu,
+    BF16 bits) on `stream` (a torch stream or raw handle; None: null stream)."""
+    lib = load_library()
+    if not hasattr(lib, "_gemm_dev_typed"):
+        P = ctypes.c_void_p
+        lib.lts_nn_gemm_bf16_device.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        lib.lts_nn_gemm_bf16_device.restype = ctypes.c_int
+        lib._gemm_dev_typed = True
+    N, K = A.shape
+    assert tuple(W.shape) == (K, 64) and A.is_contiguous() and W.is_contiguous()
+    assert A.element_size() == 2 and W.element_size() == 2
+    for Y, size in ((Y_f32, 4), (Y_bf16, 2)):
+        assert Y is None or (tuple(Y.shape) == (N, 64) and Y.is_contiguous()
+                             and Y.element_size() == size)
+    sp = getattr(stream, "cuda_stream", stream)
+    dp = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    st = lib.lts_nn_gemm_bf16_device(dp(A), N, K, dp(W), dp(bias), dp(Y_f32), dp(Y_bf16),
+                                     None if sp is None else ctypes.c_void_p(sp))
+    if st != LTS_OK:
+        raise LTSError(st, "lts_nn_gemm_bf16_device")
 
 
 def nn_gemm_tn_bf16(A_bits, D_bits, device: int = 0):

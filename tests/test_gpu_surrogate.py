@@ -70,6 +70,32 @@ def test_mfma_gemm_layout(N, K):
     assert np.all(np.abs(Y - ref) <= bound)
 
 
+@pytest.mark.parametrize("N,K", [(61419, 128), (333, 16), (0, 32)])
+def test_mfma_gemm_device_form(N, K):
+    """The device-pointer entry point: its FP32 output equals the host entry
+    point's bit for bit (same kernel, same operands) and its BF16 output is
+    relu of that value rounded to nearest even; N = 0 writes nothing."""
+    import torch
+    say("gemm device", N, K)
+    rng = np.random.default_rng(N + 7 * K)
+    A = bf16_round(rng.standard_normal((N, K)))
+    W = bf16_round(rng.standard_normal((K, 64)) / math.sqrt(K))
+    b = rng.standard_normal(64).astype(np.float32)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    Yf = torch.full((N, 64), -7.0, dtype=torch.float32, device="cuda")
+    Yb = torch.full((N, 64), 12345, dtype=torch.int16, device="cuda")
+    s = torch.cuda.Stream()
+    lts.nn_gemm_bf16_device(dev(bf16_bits(A).view(np.int16)), dev(bf16_bits(W).view(np.int16)),
+                            Y_f32=Yf, Y_bf16=Yb, bias=dev(b), stream=s)
+    s.synchronize()
+    if N == 0:
+        return
+    Y = lts.nn_gemm_bf16(bf16_bits(A), bf16_bits(W), b)
+    assert np.array_equal(Yf.cpu().numpy(), Y)
+    want = bf16_bits(np.maximum(Y, 0.0)).view(np.int16)
+    assert np.array_equal(Yb.cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("N,K", [(1000, 128), (37, 16), (1100, 64)])
 def test_mfma_gemm_tn_layout(N, K):
     say("gemm_tn", N, K)

@@ -655,48 +655,48 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     const T hi = hr ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
     T qprev = q[(size_t)voc[(size_t)i * G + n - 1] * L + l];
+    // Every slot, padding included: padding slots repeat the last slot's
+    // indices with zero coefficients, so they add exact zeros to the sums
+    // and only their stores are skipped.  Without a branch per slot all the
+    // slots' loads can be in flight together.
     T X1[G], X2[G], qtA[G];
     T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        if (a < n) {
-            const size_t o = (size_t)i * G + a;
-            const int e = eoc[o], nb = coc[o];
-            const T ue = u[(size_t)e * L + l];
-            const T hn0 = h[(size_t)nb * L + l];
-            const T hn = hr ? href[nb] + hn0 : hn0;
-            const T qa = q[(size_t)voc[o] * L + l];
-            const T qt = T(0.5) * (qprev + qa);
-            qprev = qa;
-            X1[a] = nl[o] * (T(0.5) * (hi + hn) * ue);
-            X2[a] = X1[a] * qt;
-            qtA[a] = qt;
-            K += kc[o] * ue * ue;
-            const T Sb = S;
-            S += kf[o];
-            t1 += X1[a];
-            t2 += X2[a];
-            p1 += Sb * X1[a];
-            p2 += Sb * X2[a];
-        }
+        const size_t o = (size_t)i * G + a;
+        const int e = eoc[o], nb = coc[o];
+        const T ue = u[(size_t)e * L + l];
+        const T hn0 = h[(size_t)nb * L + l];
+        const T hn = hr ? href[nb] + hn0 : hn0;
+        const T qa = q[(size_t)voc[o] * L + l];
+        const T qt = T(0.5) * (qprev + qa);
+        qprev = qa;
+        X1[a] = nl[o] * (T(0.5) * (hi + hn) * ue);
+        X2[a] = X1[a] * qt;
+        qtA[a] = qt;
+        K += kc[o] * ue * ue;
+        const T Sb = S;
+        S += kf[o];
+        t1 += X1[a];
+        t2 += X2[a];
+        p1 += Sb * X1[a];
+        p2 += Sb * X2[a];
     }
     const T phi = g * (h[il] + m.beta[i]) + K;
     T c1 = 0, c2 = 0, Sr = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        if (a < n) {
-            const size_t o = (size_t)i * G + a;
-            const T Sb = Sr;
-            Sr += kf[o];
-            c1 += X1[a];
-            c2 += X2[a];
-            const T P1 = (Sb - T(0.5)) * (t1 - X1[a]) - (p1 - Sb * X1[a]) + S * (t1 - c1);
-            const T P2 = (Sb - T(0.5)) * (t2 - X2[a]) - (p2 - Sb * X2[a]) + S * (t2 - c2);
-            const T ndo = nd[o];
-            if (act)
-                zs[(ndo > T(0) ? 0 : (size_t)m.nE * L) + (size_t)eoc[o] * L + l] =
-                    ndo * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
-        }
+        const size_t o = (size_t)i * G + a;
+        const T Sb = Sr;
+        Sr += kf[o];
+        c1 += X1[a];
+        c2 += X2[a];
+        const T P1 = (Sb - T(0.5)) * (t1 - X1[a]) - (p1 - Sb * X1[a]) + S * (t1 - c1);
+        const T P2 = (Sb - T(0.5)) * (t2 - X2[a]) - (p2 - Sb * X2[a]) + S * (t2 - c2);
+        const T ndo = nd[o];
+        if (act && a < n)
+            zs[(ndo > T(0) ? 0 : (size_t)m.nE * L) + (size_t)eoc[o] * L + l] =
+                ndo * (phi + T(0.5) * qtA[a] * P1 + T(0.5) * P2);
     }
     if (act) epilogue_l(i, l, L, -t1 / m.area[i], s0, s1, flag);
 }

@@ -1,6 +1,8 @@
 // HIP kernels for the TRiSK right-hand side and the LTS3 stage machinery on
-// gfx950 (MI355X).  One thread per target element, 256-thread blocks (four
-// wave64s), structure-of-arrays gathers.
+// gfx950 (MI355X).  256-thread blocks (four wave64s), structure-of-arrays
+// gathers; one thread per vertex or edge, one lane per edge slot of a cell
+// (8 or 16 lanes per cell); the layered forms further down map threads to
+// (element, layer).
 //
 // The right-hand side of eq:sweTimeStepping is evaluated in three kernels:
 //   k_vertex: potential vorticity q_v = (f_v + zeta_v)/h_v at vertices, with

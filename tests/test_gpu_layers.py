@@ -132,15 +132,15 @@ def test_layers_rhs_and_identical_layers(case):
     one.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_many_layers_wave_map(case, prec):
-    """70 layers take the wave-per-cell map of the layered kernels (one full
-    chunk of 64 layers and a ragged chunk of 6).  The three states of the
+@pytest.mark.parametrize("prec,nl", [("fp64", 70), ("fp32", 70), ("fp64", 56), ("fp64", 64)])
+def test_many_layers_wave_map(case, prec, nl):
+    """From 56 layers on the layered kernels take the wave-per-cell map: 56
+    (the first count that does, one ragged chunk), 64 (one full chunk) and
+    70 (a full chunk and a ragged chunk of 6).  The three states of the
     fixture repeat over the layers: every layer matches the oracle run of its
     state, and layers with the same state agree bit for bit whatever their
     lane."""
     m, fm, o, R, hs, us, dt = case
-    nl = 70
     say("many layers", prec, nl)
     c = lts.LTSContext(0, prec, layers=nl)
     c.upload_mesh(m, fm, 2, 2)

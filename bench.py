@@ -279,9 +279,9 @@ def main():
         eps = 2.0 * err[f"lts3_{prec}"]
 
         def at(kind, k):
-            c = make(prec if kind == "lts3" else "fp64")
-            n = round(K / k) if kind == "lts3" else round(K * M / k)
-            if kind == "lts3":
+            c = make(prec if kind == "lts3" else other if kind == "lts3_other" else "fp64")
+            n = round(K / k) if kind.startswith("lts3") else round(K * M / k)
+            if kind.startswith("lts3"):
                 go = lambda j: c.step(k * dt, M, j)
             elif kind == "rk4":
                 go = lambda j: c.step_scheme("rk4", k * dt / M, 1, j)
@@ -305,10 +305,11 @@ def main():
         factors = (1.0, 1.25, 4.0 / 3.0, 1.6, 2.0, 2.5, 3.2, 4.0, 5.0, 8.0)
         tts = {"eps": eps,
                "lts3": [at("lts3", k) for k in factors[:9] if whole(K, k)],
+               f"lts3_{other}": [at("lts3_other", k) for k in factors[:9] if whole(K, k)],
                "rk3_fp64": [at("rk3", k) for k in factors if whole(K * M, k)],
                "rk4_fp64": [at("rk4", k) for k in factors if whole(K * M, k)]}
         best = {}
-        for kind in ("lts3", "rk3_fp64", "rk4_fp64"):
+        for kind in ("lts3", f"lts3_{other}", "rk3_fp64", "rk4_fp64"):
             ok = [r["ms"] for r in tts[kind] if r["ms"] is not None and r["err"] <= eps]
             best[kind] = min(ok) if ok else None
         tts["best_ms"] = best
@@ -316,6 +317,9 @@ def main():
                                 if best["lts3"] and best["rk3_fp64"] else None)
         tts["rk4_over_lts3"] = (round(best["rk4_fp64"] / best["lts3"], 3)
                                 if best["lts3"] and best["rk4_fp64"] else None)
+        fast = min((b for b in (best["lts3"], best[f"lts3_{other}"]) if b), default=None)
+        slow = min((b for b in (best["rk3_fp64"], best["rk4_fp64"]) if b), default=None)
+        tts["best_global_fp64_over_best_lts3"] = round(slow / fast, 3) if fast and slow else None
         log("time to solution:", json.dumps(tts))
         c32.close(), ref.close()
         ctx.init_state(w.h0, w.u0)

@@ -230,6 +230,7 @@ struct Run {
         g.xcur = xcur;
         g.a_cur = (T)a_cur;
         g.a_dt = (T)a_dt;
+        g.convex = xold && xcur && a_old + a_cur == 1.0;
         return g;
     }
     static Seg<T> mirror(Seg<T> g, int mlo, int mhi, T* mnew, T* mcur) {

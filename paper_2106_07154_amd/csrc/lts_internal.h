@@ -48,7 +48,12 @@ struct DevMesh {
 };
 
 // One epilogue segment: targets [lo, hi) of a tendency kernel.
-//   mode 1 (update):     out[j] = a_old*xold[j] + a_cur*xcur[j] + a_dt*G
+//   mode 1 (update):     out[j] = a_old*xold[j] + a_cur*xcur[j] + a_dt*G, or,
+//                        when a_old + a_cur = 1 (convex), the same as
+//                        xold[j] + a_cur*(xcur[j] - xold[j]) + a_dt*G: exact
+//                        for xold = xcur whatever the rounding of a_old and
+//                        a_cur (in FP32, 1/3 + 2/3 rounds to 1 + 3e-8, which
+//                        the first form would apply to the state every step)
 //   mode 2 (accumulate): acc[j-lo] = (first ? 0 : acc[j-lo]) + theta*G
 //   mode 1 with acc != nullptr also accumulates theta*G into acc (the RK4
 //   stage sum).
@@ -62,6 +67,7 @@ struct Seg {
     const T* xold = nullptr;
     const T* xcur = nullptr;
     T a_old = 0, a_cur = 0, a_dt = 0;
+    int convex = 0;
     T* acc = nullptr;
     T theta = 0;
     int mlo = 0, mhi = 0;

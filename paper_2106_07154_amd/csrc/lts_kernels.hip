@@ -84,7 +84,10 @@ __device__ __forceinline__ void apply_seg(int j, T G, const Seg<T>& s, const Epi
     T v;
     if (s.mode == 1) {
         v = s.a_dt * G;
-        if (s.xold) {
+        if (s.convex) {
+            const T xo = PRE ? r.xo : s.xold[j];
+            v = xo + s.a_cur * ((PRE ? r.xc : s.xcur[j]) - xo) + v;
+        } else if (s.xold) {
             const T xo = PRE ? r.xo : s.xold[j];
             v = s.a_old * xo + (s.xcur ? s.a_cur * (PRE ? r.xc : s.xcur[j]) : T(0)) + v;
         } else if (s.xcur) {
@@ -549,7 +552,8 @@ __device__ __forceinline__ void apply_seg_l(int j, int l, int L, T G, const Seg<
     T v;
     if (s.mode == 1) {
         v = s.a_dt * G;
-        if (s.xold) v = s.a_old * s.xold[f] + (s.xcur ? s.a_cur * s.xcur[f] : T(0)) + v;
+        if (s.convex) v = s.xold[f] + s.a_cur * (s.xcur[f] - s.xold[f]) + v;
+        else if (s.xold) v = s.a_old * s.xold[f] + (s.xcur ? s.a_cur * s.xcur[f] : T(0)) + v;
         else if (s.xcur) v = s.a_cur * s.xcur[f] + v;
         s.out[f] = v;
         if (j >= s.mlo && j < s.mhi) {

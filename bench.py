@@ -263,13 +263,16 @@ def main():
                        "H the median initial depth"}
         log("errors:", json.dumps(err))
         v_fp32 = value if prec == "fp32" else v32
+        # RHS cell evaluations of one LTS3 coarse step: 3|C| + (2 + 3M)|I| + 3M|F| + |F_bar|
+        evals_per_step = (3 * int(cells[0]) + (2 + 3 * M) * int(cells[1] + cells[2])
+                          + 3 * M * int(cells[3]) + int(fbar[0]))
         out["comparisons"] = {"rk3_fp64_value": round(v_rk, 1),
                               "lts3_over_rk3": round(value / v_rk, 3),
                               f"lts3_{other}_value": round(v32, 1),
                               "fp32_over_rk3_fp64": round(v_fp32 / v_rk, 3),
-                              "ideal_work_ratio": round(
-                                  3 * M * m.nCells / (3 * int(cells[0]) + (2 + 3 * M) * int(cells[1] + cells[2])
-                                                      + 3 * M * int(cells[3]) + int(fbar[0])), 3),
+                              "ideal_work_ratio": round(3 * M * m.nCells / evals_per_step, 3),
+                              # cell-tendency evaluations LTS3 actually performs per second
+                              "lts3_work_rate_cell_evals_per_s": round(evals_per_step * K * L / (ms / 1e3), 1),
                               "l2_height_error": err,
                               "time_to_solution": None,
                               "mass_rel_drift": None}

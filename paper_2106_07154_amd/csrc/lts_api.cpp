@@ -269,7 +269,7 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     std::vector<int32_t> nEoC(nC), eoc((size_t)mx * nC, 0), coc((size_t)mx * nC, 0),
         voc((size_t)mx * nC, 0);
     std::vector<double> nl((size_t)mx * nC, 0), nd((size_t)mx * nC, 0), kc((size_t)mx * nC, 0),
-        kf((size_t)mx * nC, 0), area(nC), bot(nC);
+        kf((size_t)mx * nC, 0), sb((size_t)mx * nC, 0), sn(nC), area(nC), rarea(nC), bot(nC);
     for (int ni = 0; ni < nC; ++ni) {
         const int i = c->cperm[ni];
         const int n = m->n_edges_on_cell[i];
@@ -299,6 +299,14 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
             coc[o] = coc[ol];
             voc[o] = voc[ol];
         }
+        // counter-clockwise prefix sums of the kite fractions (FP64)
+        double S = 0.0;
+        for (int j = 0; j < mx; ++j) {
+            sb[(size_t)ni * mx + j] = S;
+            S += kf[(size_t)ni * mx + j];
+        }
+        sn[ni] = S;
+        rarea[ni] = 1.0 / m->area_cell[i];
     }
     std::vector<int32_t> eov((size_t)3 * nV), cov((size_t)3 * nV);
     std::vector<double> tdc((size_t)3 * nV), kite((size_t)3 * nV), fA(nV);
@@ -330,7 +338,10 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     if ((s = upload_vec<T>(c, &dm->nd, conv<T>(nd)))) return s;
     if ((s = upload_vec<T>(c, &dm->kc, conv<T>(kc)))) return s;
     if ((s = upload_vec<T>(c, &dm->kf, conv<T>(kf)))) return s;
+    if ((s = upload_vec<T>(c, &dm->sb, conv<T>(sb)))) return s;
+    if ((s = upload_vec<T>(c, &dm->sn, conv<T>(sn)))) return s;
     if ((s = upload_vec<T>(c, &dm->area, conv<T>(area)))) return s;
+    if ((s = upload_vec<T>(c, &dm->rarea, conv<T>(rarea)))) return s;
     if ((s = upload_vec<T>(c, &dm->bot, conv<T>(bot)))) return s;
     c->bot_perm = bot;
     c->area_perm = area;

@@ -138,8 +138,11 @@ double kernel_bytes(const PassPlan& P, int kclass, const Seg<T>& s0, const Seg<T
     if (kclass == KC_VERTEX)
         return (P.v_hi - P.v_lo) * (3 * 4 * 2 + 7 * ts) +
                L * ((P.v_hi - P.v_lo) * ts + (P.v_uniq_u + P.v_uniq_h) * ts);
+    // per cell: n_i, beta_i and A_i, plus S_n in the single-layer kernel (the
+    // layered one sums the kite fractions itself); per slot: three indices
+    // and four coefficients
     if (kclass == KC_CELL)
-        return (P.c_hi - P.c_lo) * (4 + 2 * ts) + P.c_slots * (3 * 4 + 4 * ts) +
+        return (P.c_hi - P.c_lo) * (4 + (L > 1 ? 2 : 3) * ts) + P.c_slots * (3 * 4 + 4 * ts) +
                L * (P.c_slots * ts + (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts +
                     seg_bytes(s0) + seg_bytes(s1));
     return L * ((P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(s0) + seg_bytes(s1)) +

@@ -31,7 +31,11 @@ struct DevMesh {
     const T* nd;           // [nC][G] n_{e,i} / d_e
     const T* kc;           // [nC][G] l_e d_e / (4 A_i)
     const T* kf;           // [nC][G] A_{i,v_j} / A_i (kite fraction of vertex slot j)
+    const T* sb;           // [nC][G] S_j: kite fractions of the slots before j summed
+                           //         (padding slots: S_n)
+    const T* sn;           // [nC] S_n: all kite fractions of the cell summed
     const T* area;         // [nC] A_i
+    const T* rarea;        // [nC] 1 / A_i
     const T* bot;          // [nC] b_i (diagnostics)
     // Thickness storage.  href == nullptr: the state holds h itself and
     // beta = b.  Otherwise the state holds eta = h - href (perturbation form,

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __rest
 // valid indices (copies of slot n-1) and zero coefficients.
 //
 // The PV part of Z_i(b) is rewritten with prefix sums: with S_a the kite
-// fractions summed counter-clockwise before slot a and S_n their total,
+// fractions summed counter-clockwise before slot a and S_n their total (both
+// mesh constants, tabulated at upload),
 //   R_ab - 1/2 = (S_b - 1/2) - S_a + S_n [a > b],
 // so for any slot quantity X
 //   sum_{a != b} (R_ab - 1/2) X_a = (S_b - 1/2)(sum X - X_b)
@@ -246,7 +247,7 @@ struct CellLane {
     size_t o;  // slot-table entry
     int i, lane, n, e;
     bool live;
-    T nl, kc, kf, nd, hi, hn, hc, ue, bi, ai;
+    T nl, kc, sb, sn, nd, hi, hn, hc, ue, bi, ra;
     EpiIn<T> ep;
 };
 
@@ -269,9 +270,10 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     const int nb = m.coc[c.o];
     c.nl = m.nl[c.o];
     c.kc = m.kc[c.o];
-    c.kf = m.kf[c.o];
+    c.sb = m.sb[c.o];
     c.nd = m.nd[c.o];
     c.n = m.nEoC[i];
+    c.sn = m.sn[i];
     c.hc = h[i];
     c.hi = hr ? href[i] + c.hc : c.hc;
     c.hn = hr ? href[nb] + h[nb] : h[nb];
@@ -281,7 +283,7 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     c.ep = EpiIn<T>{};
     if (PRE) c.ep = epi_loads(i, s0, s1, h);
     c.bi = m.beta[i];
-    c.ai = m.area[i];
+    c.ra = m.rarea[i];
     return c;
 }
 
@@ -293,22 +295,22 @@ __device__ __forceinline__ void cell_math(const DevMesh<T>& m, CellLane<T> c, T 
     const int lane = c.lane;
     const T Ga = c.nl * (T(0.5) * (c.hi + c.hn) * c.ue);
     const T K = gsum<T, G>(c.kc * c.ue * c.ue);
-    const T Sinc = gscan<T, G>(c.kf, lane);
-    const T Sb = Sinc - c.kf;                    // S_b: fractions before slot b
-    const T Sn = gsum<T, G>(c.kf);               // S_n
+    const T Sb = c.sb, Sn = c.sn;  // S_b and S_n from the slot tables
     const T qt = T(0.5) * (gprev<T, G>(qv, lane) + qv);
     const T X1 = Ga, X2 = Ga * qt;
     const T c1 = gscan<T, G>(X1, lane), c2 = gscan<T, G>(X2, lane);
     const T t1 = gsum<T, G>(X1), t2 = gsum<T, G>(X2);  // sums; t1 = sum G
     const T p1 = gsum<T, G>(Sb * X1), p2 = gsum<T, G>(Sb * X2);
-    const T P1 = (Sb - T(0.5)) * (t1 - X1) - (p1 - Sb * X1) + Sn * (t1 - c1);
-    const T P2 = (Sb - T(0.5)) * (t2 - X2) - (p2 - Sb * X2) + Sn * (t2 - c2);
+    // (S_b - 1/2)(t - X_b) - (p - S_b X_b) + S_n (t - c_b), collected:
+    const T w = Sb + Sn - T(0.5);
+    const T P1 = w * t1 + T(0.5) * X1 - p1 - Sn * c1;
+    const T P2 = w * t2 + T(0.5) * X2 - p2 - Sn * c2;
     if (PRE) {
         // Uses outside the conditional stores below keep these loads with
         // the others at the top; sunk into the stores, each would add a
         // dependent memory round trip.
         hold(c.bi);
-        hold(c.ai);
+        hold(c.ra);
         hold(c.nd);
         hold(c.ep.xo);
         hold(c.ep.xc);
@@ -319,8 +321,8 @@ __device__ __forceinline__ void cell_math(const DevMesh<T>& m, CellLane<T> c, T 
         zs[(c.nd > T(0) ? 0 : (size_t)m.nE) + c.e] =
             c.nd * (phi + T(0.5) * qt * P1 + T(0.5) * P2);
     if (c.live && lane == 0) {
-        if (PRE) epilogue(c.i, -t1 / c.ai, s0, s1, c.ep, flag);
-        else epilogue(c.i, -t1 / c.ai, s0, s1, flag);
+        if (PRE) epilogue(c.i, -t1 * c.ra, s0, s1, c.ep, flag);
+        else epilogue(c.i, -t1 * c.ra, s0, s1, flag);
     }
 }
 

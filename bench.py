@@ -16,6 +16,7 @@ Reported (one JSON line on stdout):
              after the timed region), against 8 TB/s
   cpu_baseline  the FP64 oracle on the host, one thread, on a bounded number
              of coarse steps of the same workload
+Non-finite values (the error of a run past its stability limit) print as null.
 """
 import argparse
 import json
@@ -33,6 +34,22 @@ METRIC = "cell-updates/s, LTS3 vs global RK3 on 1 GPU at fixed L2 height error; 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def strict(x):
+    """x with every non-finite float replaced by None, so the result line is
+    strict JSON (a run that blew up reports "err": null)."""
+    if isinstance(x, float):
+        return x if math.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: strict(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [strict(v) for v in x]
+    return x
+
+
+def emit(out):
+    print(json.dumps(strict(out), allow_nan=False), flush=True)
 
 
 def rel_l2(a, b, w):
@@ -366,7 +383,7 @@ def main():
                                          f"{w.name} in {tc:.1f}s on {os.cpu_count()} host cores "
                                          f"(1 used)"}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def bench_ensemble(args):
@@ -458,7 +475,7 @@ def bench_ensemble(args):
                                 "l2_height_error_sampled": errs,
                                 "reference": "FP64 SSPRK3 at a quarter of each member's fine step"}}
     ens.close()
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 
@@ -533,7 +550,7 @@ def bench_gemm(args):
                             "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
                             "sample": f"the oracle's FP64 layer product on {n_s} rows "
                                       f"x {reps} repetitions, scaled to {N} rows"}}
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def bench_surrogate(args):
@@ -711,7 +728,7 @@ def bench_surrogate(args):
            "epsilon": eps}
     sur.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 if __name__ == "__main__":

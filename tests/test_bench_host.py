@@ -32,3 +32,11 @@ def test_traffic_lookup_is_gated_by_source_hash(tmp_path, monkeypatch):
     assert bench.measured_traffic("vertex_pv", "wl") is None
     assert bench.measured_traffic("cell_tendency", "missing") is None
 
+
+
+def test_result_line_is_strict_json():
+    """A blown-up run's error (inf or nan) prints as null, not as the
+    non-standard Infinity/NaN tokens."""
+    out = {"a": float("inf"), "b": [1.5, float("nan"), {"c": -float("inf")}], "d": 2, "e": "x"}
+    s = json.dumps(bench.strict(out), allow_nan=False)
+    assert json.loads(s) == {"a": None, "b": [1.5, None, {"c": None}], "d": 2, "e": "x"}

@@ -47,6 +47,11 @@ def _cases(request):
     m = request.getfixturevalue("lloyd_mesh")
     out.append((m, (np.hypot(m.xCell - 2e5, m.yCell - 2e5) < 5e4).astype(np.uint8), 2, 2))
     out.append((m, (np.hypot(m.xCell - 2e5, m.yCell - 2e5) < 5e4).astype(np.uint8), 1, 3))
+    # one 11-gon (16-slot tables), inside the fine disk
+    m = request.getfixturevalue("ring_mesh")
+    c11 = int(np.argmax(m.nEdgesOnCell))
+    fm = (np.hypot(m.xCell - m.xCell[c11], m.yCell - m.yCell[c11]) < 2.5e4).astype(np.uint8)
+    out.append((m, fm, 2, 2))
     return out
 
 

@@ -126,7 +126,9 @@ lts_status lts_get_regions(lts_ctx *ctx, int8_t *cell_region, int8_t *edge_regio
 lts_status lts_init_state(lts_ctx *ctx, const double *h, const double *u, double t0);
 
 /* Same from device arrays in the context precision (caller numbering); they
-   are read only during the call. */
+   are read only during the call.  A set-up path, not a fast path: the arrays
+   are staged through host memory (synchronous copies), where the FP32 form's
+   reference thickness is derived from them exactly as for lts_init_state. */
 lts_status lts_init_state_device(lts_ctx *ctx, const void *d_h, const void *d_u, double t0);
 
 /* Advance n_steps coarse steps of LTS3 (Algorithm 2.2, order 3) with coarse
@@ -163,7 +165,8 @@ lts_status lts_diagnostics(lts_ctx *ctx, lts_diag *out);
 /* Copy the state to host doubles (caller numbering; synchronises). */
 lts_status lts_get_state(lts_ctx *ctx, double *h, double *u);
 
-/* Copy the state to device arrays in the context precision (caller numbering). */
+/* Copy the state to device arrays in the context precision (caller numbering;
+   staged through host memory like lts_init_state_device; synchronises). */
 lts_status lts_get_state_device(lts_ctx *ctx, void *d_h, void *d_u);
 
 /* Per-kernel timing: when enabled, steps launch without graphs and every

@@ -16,6 +16,9 @@ Reported (one JSON line on stdout):
              after the timed region), against 8 TB/s
   cpu_baseline  the FP64 oracle on the host, one thread, on a bounded number
              of coarse steps of the same workload
+  paper_metrics  the paper's own measures of the workload and run (Section 4):
+             its ideal LTS speed-up ("optimal ratio"), C_cf, A_ls, and the
+             gain of LTS3 over RK4 in percent at equal L2 height error
 Non-finite values (the error of a run past its stability limit) print as null.
 """
 import argparse
@@ -50,6 +53,31 @@ def strict(x):
 
 def emit(out):
     print(json.dumps(strict(out), allow_nan=False), flush=True)
+
+
+# The paper's measurement definitions (Section 4).  "Coarse time-step cells"
+# are the coarse region and both interface layers; "fine time-step cells" F.
+def paper_optimal_ratio(coarse_step_cells, fine_cells, M):
+    """Ideal LTS speed-up of Section 4.3 (Table 3's optimal rate): the cells a
+    global scheme advances at the fine step, M times per coarse step, over the
+    cells LTS advances (coarse-step cells once, fine cells M times).  The
+    paper states it for M = 4."""
+    return M * (coarse_step_cells + fine_cells) / (coarse_step_cells + M * fine_cells)
+
+
+def coarse_fine_ratio(coarse_step_cells, fine_cells):
+    """C_cf of Section 4.4: coarse time-step cells over fine time-step cells."""
+    return coarse_step_cells / fine_cells
+
+
+def area_ratio(area_cell):
+    """A_ls of Section 4.4: area of the largest cell over that of the smallest."""
+    return float(area_cell.max() / area_cell.min())
+
+
+def gain_percent(t_rk4, t_lts):
+    """CPU-time gain of LTS over RK4 in percent, as in Section 4.4 / Table 4."""
+    return (t_rk4 - t_lts) * 100.0 / t_rk4
 
 
 def rel_l2(a, b, w):
@@ -244,6 +272,10 @@ def main():
                                        "I2": int(cells[1]), "C": int(cells[0]),
                                        "Fbar": int(fbar[0])}},
            "roofline": roofline, "kernels": kernels}
+    n_cs, n_f = int(cells[0] + cells[1] + cells[2]), int(cells[3])
+    out["paper_metrics"] = {"optimal_ratio": round(paper_optimal_ratio(n_cs, n_f, M), 3),
+                            "C_cf": round(coarse_fine_ratio(n_cs, n_f), 3),
+                            "A_ls": round(area_ratio(m.areaCell), 3)}
 
     if not args.quick:
         # global SSPRK3 at the fine step over the same simulated time
@@ -342,6 +374,10 @@ def main():
         fast = min((b for b in (best["lts3"], best[f"lts3_{other}"]) if b), default=None)
         slow = min((b for b in (best["rk3_fp64"], best["rk4_fp64"]) if b), default=None)
         tts["best_global_fp64_over_best_lts3"] = round(slow / fast, 3) if fast and slow else None
+        for kind in ("lts3", f"lts3_{other}"):
+            if best[kind] and best["rk4_fp64"]:
+                out["paper_metrics"][f"gain_percent_{kind}_vs_rk4_fp64"] = round(
+                    gain_percent(best["rk4_fp64"], best[kind]), 2)
         log("time to solution:", json.dumps(tts))
         c32.close(), ref.close()
         ctx.init_state(w.h0, w.u0)

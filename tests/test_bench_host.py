@@ -40,3 +40,40 @@ def test_result_line_is_strict_json():
     out = {"a": float("inf"), "b": [1.5, float("nan"), {"c": -float("inf")}], "d": 2, "e": "x"}
     s = json.dumps(bench.strict(out), allow_nan=False)
     assert json.loads(s) == {"a": None, "b": [1.5, None, {"c": None}], "d": 2, "e": "x"}
+
+
+def _golden():
+    with open(os.path.join(ROOT, "tests", "golden", "paper_cost_metrics.json")) as f:
+        return json.load(f)
+
+
+def test_paper_optimal_ratio_matches_printed_value():
+    """The paper's worked example of its ideal LTS speed-up (fixture cites it):
+    474,467 coarse time-step cells, 146,540 fine ones, M = 4 -> 2.342."""
+    g = _golden()["optimal_ratio"]
+    r = bench.paper_optimal_ratio(g["coarse_step_cells"], g["fine_cells"], g["M"])
+    assert round(r, g["decimals"]) == g["value"]
+    # M = 1 gains nothing; all cells fine gains nothing
+    assert bench.paper_optimal_ratio(1000, 500, 1) == 1.0
+    assert bench.paper_optimal_ratio(0, 500, 8) == 1.0
+
+
+def test_paper_cell_ratio_and_gain_match_printed_values():
+    """C_cf of the three region setups and the gain column of the RK4
+    comparison table, recomputed from the printed cell counts and CPU times.
+    The printed gains are cut to three decimals from the unrounded times, so
+    they are held to one unit in the last place."""
+    g = _golden()
+    for c in g["C_cf"]["cases"]:
+        assert abs(bench.coarse_fine_ratio(c["coarse_step_cells"], c["fine_cells"]) - c["value"]) < 1e-3
+    for c in g["gain_percent"]["cases"]:
+        for t, want in zip(c["lts3"], c["gain"]):
+            assert abs(bench.gain_percent(c["rk4"], t) - want) < 1e-3, (c["ranks"], t)
+
+
+def test_area_ratio():
+    import numpy as np
+    from paper_2106_07154_amd.inputs import periodic_hex_mesh
+    m = periodic_hex_mesh(8, 8, 1.0e4)
+    assert abs(bench.area_ratio(m.areaCell) - 1.0) < 1e-12
+    assert bench.area_ratio(np.array([2.0, 0.5, 1.0])) == 4.0

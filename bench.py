@@ -157,6 +157,12 @@ def main():
                     help="target duration of the oracle CPU-baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="LTS3 FP64 timed region only (for profiler runs)")
+    ap.add_argument("--max-dt", action="store_true",
+                    help="the paper's maximum-time-step test instead of the throughput line: "
+                         "largest stable fine step (M = 1), then the largest M, against global "
+                         "RK4 and SSPRK3 at their largest stable steps")
+    ap.add_argument("--max-dt-hours", type=float, default=1.0,
+                    help="simulated time of every run of the maximum-time-step test")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -222,6 +228,11 @@ def main():
         c.upload_mesh(m, w.fine_mask, w.n_if1, w.n_if2, w.gravity)
         c.init_state(h0, u0)
         return c
+
+    if args.max_dt:
+        if L > 1:
+            sys.exit("--max-dt runs on one layer")
+        return bench_max_dt(args, w, make, lts, torch, stream, prec, h0, u0)
 
     ctx = make(prec)
     cells, edges, fbar = ctx.region_counts()
@@ -419,6 +430,121 @@ def main():
                                          f"{w.name} in {tc:.1f}s on {os.cpu_count()} host cores "
                                          f"(1 used)"}
     ctx.close()
+    emit(out)
+
+
+def bench_max_dt(args, w, make, lts, torch, stream, prec, h0, u0):
+    """The paper's maximum-time-step test (Section 4.4, Tables 4 and 5).
+
+    The largest stable fine step is found with M = 1 (where LTS3 is SSPRK3),
+    then M is raised at that fine step until LTS3 fails; global FP64 RK4 and
+    SSPRK3 get their own largest stable steps.  A run is stable when it ends
+    finite with max h - min h at most twice its initial value after the whole
+    simulated time.  Steps are searched by doubling from the workload's
+    operating step and bisecting (geometrically) to 0.5 %.  Each method is
+    then timed over the same simulated time at its largest stable step, with
+    its L2 height error against FP64 SSPRK3 at a quarter of the operating fine
+    step, and the gain over RK4 is (T_RK4 - T_LTS3) * 100 / T_RK4."""
+    import numpy as np
+    m = w.mesh
+    T = args.max_dt_hours * 3600.0
+    dt_op = w.dt_coarse / w.M
+    ctx = {"lts3": make(prec), "fp64": make("fp64")}
+    d0 = ctx["fp64"].diagnostics()
+    spread0 = d0.h_max - d0.h_min
+
+    def steps(dt):
+        return int(math.ceil(T / dt - 1e-9))
+
+    def run(kind, dt, M=1):
+        """Context, stepper and step count for a run over exactly T: the step
+        (coarse step for LTS3) is T / n with n = ceil(T / (M dt)), so it never
+        exceeds the one asked for."""
+        c = ctx["lts3" if kind == "lts3" else "fp64"]
+        n = steps(M * dt)
+        big = T / n
+        if kind == "lts3":
+            return c, lambda k: c.step(big, M, k), n
+        if kind == "rk4":
+            return c, lambda k: c.step_scheme("rk4", big, 1, k), n
+        return c, lambda k: c.step_rk3(big, k), n
+
+    def stable(kind, dt, M=1):
+        c, go, n = run(kind, dt, M)
+        c.init_state(h0, u0)
+        try:
+            go(n)
+        except lts.LTSError:
+            return False
+        st, d = c.diagnostics_status()
+        return st == 0 and (d.h_max - d.h_min) <= 2.0 * spread0
+
+    def largest(ok, lo):
+        if not ok(lo):
+            raise RuntimeError("the workload's operating step is not stable over the run")
+        hi = 2.0 * lo
+        while hi < 1e3 * dt_op and ok(hi):
+            lo, hi = hi, 2.0 * hi
+        while hi / lo > 1.005:
+            mid = math.sqrt(lo * hi)
+            lo, hi = (mid, hi) if ok(mid) else (lo, mid)
+        return lo
+
+    t0 = time.time()
+    dt_f = largest(lambda x: stable("lts3", x, 1), dt_op)
+    M_max = 1
+    while M_max < 200 and stable("lts3", dt_f, M_max + 1):
+        M_max += 1
+    dt_rk4 = largest(lambda x: stable("rk4", x), dt_op)
+    dt_rk3 = largest(lambda x: stable("rk3", x), dt_op)
+    log(f"max dt search {time.time() - t0:.1f}s: fine {dt_f:.4f}s M {M_max} "
+        f"rk4 {dt_rk4:.4f}s ssprk3 {dt_rk3:.4f}s")
+
+    ref = ctx["fp64"]
+    ref.init_state(h0, u0)
+    n_ref = steps(dt_op / 4)
+    ref.step_rk3(T / n_ref, n_ref)
+    h_ref, _ = ref.get_state()
+    H = float(np.median(w.h0))
+    wA = m.areaCell
+
+    def timed_run(kind, dt, M=1):
+        c, go, n = run(kind, dt, M)
+        go(1)                            # the step's graph, outside the timing
+        c.init_state(h0, u0)
+        t = timed(torch, stream, lambda: go(n))
+        h, _ = c.get_state()
+        return {"dt_s": round(T / n, 6), "M": M, "steps": n, "ms": round(t, 3),
+                "err": rel_l2(h - H, h_ref - H, wA)}
+
+    runs = {f"lts3_{prec}": timed_run("lts3", dt_f, M_max),
+            "rk4_fp64": timed_run("rk4", dt_rk4),
+            "ssprk3_fp64": timed_run("rk3", dt_rk3)}
+    t_l, t_4 = runs[f"lts3_{prec}"]["ms"], runs["rk4_fp64"]["ms"]
+    gain = gain_percent(t_4, t_l)
+    cells = ctx["lts3"].region_counts()[0]
+    n_cs, n_f = int(cells[0] + cells[1] + cells[2]), int(cells[3])
+    for c in ctx.values():
+        c.close()
+    out = {"metric": "CPU-time gain of LTS3 over global RK4 at their largest stable time steps "
+                     "(the paper's maximum-time-step test)",
+           "value": round(gain, 2), "unit": "%", "n_gpus": 1, "steps": runs[f"lts3_{prec}"]["steps"],
+           "warmup": 1, "ms_per_step": round(t_l / runs[f"lts3_{prec}"]["steps"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": f"{w.name}-maxdt", "cells": m.nCells, "sim_hours": args.max_dt_hours,
+                      "operating_fine_dt_s": round(dt_op, 6), "interface_rings": [w.n_if1, w.n_if2]},
+           "max_dt": {"fine_s": round(T / steps(dt_f), 4), "M": M_max,
+                      "coarse_s": round(T / steps(M_max * dt_f), 4),
+                      "rk4_s": round(T / steps(dt_rk4), 4), "ssprk3_s": round(T / steps(dt_rk3), 4),
+                      "stability_test": "finite, max h - min h at most twice its initial value"},
+           "runs": runs,
+           "speedup_over_rk4": round(t_4 / t_l, 3),
+           "speedup_over_ssprk3": round(runs["ssprk3_fp64"]["ms"] / t_l, 3),
+           "paper_metrics": {"optimal_ratio_at_M": round(paper_optimal_ratio(n_cs, n_f, M_max), 3),
+                             "C_cf": round(coarse_fine_ratio(n_cs, n_f), 3),
+                             "A_ls": round(area_ratio(m.areaCell), 3),
+                             "gain_percent_vs_rk4_fp64": round(gain, 2)}}
     emit(out)
 
 

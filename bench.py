@@ -510,6 +510,7 @@ def bench_max_dt(args, w, make, lts, torch, stream, prec, h0, u0):
 
     def timed_run(kind, dt, M=1):
         c, go, n = run(kind, dt, M)
+        c.init_state(h0, u0)             # the search may have left it non-finite
         go(1)                            # the step's graph, outside the timing
         c.init_state(h0, u0)
         t = timed(torch, stream, lambda: go(n))

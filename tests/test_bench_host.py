@@ -77,3 +77,76 @@ def test_area_ratio():
     m = periodic_hex_mesh(8, 8, 1.0e4)
     assert abs(bench.area_ratio(m.areaCell) - 1.0) < 1e-12
     assert bench.area_ratio(np.array([2.0, 0.5, 1.0])) == 4.0
+
+
+def test_max_dt_search_finds_known_limits(capsys):
+    """The maximum-time-step procedure on fake contexts whose stability
+    limits are known: the largest stable steps come out within the 0.5 %
+    bisection tolerance (never above the limit), M is the largest whole
+    ratio the coarse limit allows, every run covers the same simulated time,
+    and the result line is strict JSON."""
+    import types
+    import numpy as np
+    lim = {"fine": 6.5, "coarse": 40.0, "rk4": 7.9, "rk3": 6.4}
+    T = 3600.0
+
+    class Err(Exception):
+        pass
+
+    class D:
+        def __init__(self, lo, hi):
+            self.h_min, self.h_max = lo, hi
+
+    class Ctx:
+        def __init__(self):
+            self.ok, self.sim = True, 0.0
+
+        def init_state(self, h, u):
+            self.ok, self.sim = True, 0.0
+
+        def step(self, dt, M, n):
+            self.sim += dt * n
+            self.ok &= dt / M <= lim["fine"] and dt <= lim["coarse"]
+
+        def step_scheme(self, s, dt, M, n):
+            self.sim += dt * n
+            self.ok &= dt <= lim["rk4"]
+
+        def step_rk3(self, dt, n):
+            self.sim += dt * n
+            self.ok &= dt <= lim["rk3"]
+
+        def diagnostics(self):
+            return D(495.0, 505.0)
+
+        def diagnostics_status(self):
+            return (0, D(495.0, 505.0)) if self.ok else (-4, D(0.0, 1e9))
+
+        def get_state(self):
+            assert abs(self.sim - T) < 1e-6 * T
+            return np.full(4, 500.5), None
+
+        def region_counts(self):
+            return np.array([100, 10, 10, 50]), None, np.array([5])
+
+        def close(self):
+            pass
+
+    mesh = types.SimpleNamespace(nCells=170, areaCell=np.array([1.0, 2.0, 4.0, 3.0]))
+    w = types.SimpleNamespace(mesh=mesh, name="fake", M=8, dt_coarse=8 * 2.62,
+                              h0=np.full(4, 500.0), u0=None, n_if1=2, n_if2=2)
+    saved = bench.timed
+    bench.timed = lambda torch, stream, fn: (fn(), 10.0)[1]
+    try:
+        bench.bench_max_dt(types.SimpleNamespace(max_dt_hours=1.0), w, lambda p: Ctx(),
+                           types.SimpleNamespace(LTSError=Err), None, None, "fp64", w.h0, None)
+    finally:
+        bench.timed = saved
+    line = capsys.readouterr().out.strip().splitlines()[-1]
+    out = json.loads(line)
+    md = out["max_dt"]
+    for key, want in (("fine_s", lim["fine"]), ("rk4_s", lim["rk4"]), ("ssprk3_s", lim["rk3"])):
+        assert want / 1.006 <= md[key] <= want, (key, md[key])
+    assert md["M"] == 6 and md["coarse_s"] <= lim["coarse"]
+    assert out["runs"]["lts3_fp64"]["M"] == 6
+    assert out["value"] == 0.0 and out["paper_metrics"]["C_cf"] == round(120 / 50, 3)

@@ -38,6 +38,38 @@ def test_exports_every_declared_symbol(lib):
     assert sorted(declared) == sorted(lts.EXPORTED)
 
 
+def test_headers_are_c_and_link_from_c(lib, tmp_path):
+    """The boundary is usable from plain C: both public headers compile as
+    strict C99 (and C++17), and a C program calling every declared entry point
+    links against liblts.so with unmangled names.  Nothing is run."""
+    import glob
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    text = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
+    decl = re.compile(r"^(?:lts_status|void|int|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
+                      re.M)
+    names = sorted(set(decl.findall(text)))
+    src = tmp_path / "abi.c"
+    src.write_text('#include "lts.h"\n#include "lts_surrogate.h"\n'
+                   "typedef void (*fn)(void);\n"
+                   "fn table[] = {" + ", ".join(f"(fn){n}" for n in names) + "};\n"
+                   "int main(void) { return table[0] == 0; }\n")
+    inc = os.path.join(ROOT, "include")
+    for std, extra in (("-std=c99", []), ("-std=c++17", ["-x", "c++"])):
+        cc = gcc if std == "-std=c99" else (shutil.which("g++") or gcc)
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                            *extra, "-I", inc, str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+    libdir = os.path.join(ROOT, "paper_2106_07154_amd")
+    r = subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(tmp_path / "abi"),
+                        "-L", libdir, "-l:liblts.so", "-Wl,-rpath-link,/opt/rocm/lib"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def _cases(request):
     out = []
     m = request.getfixturevalue("hex64")

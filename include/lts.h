@@ -81,6 +81,20 @@ typedef struct {
     const double *bottom;                /* [n_cells]    topography b_i        */
     const double *cell_xyz;              /* [n_cells][3] or NULL: positions, used
                                             only to order cells for locality     */
+    /* Optional MPAS tables of eq:discPV (all three NULL, or all three given
+       with max_edges2 >= 1).  The library derives the weights of eq:weights
+       itself from the kite areas and never reads these in a step; when they
+       are given, lts_upload_mesh and lts_plan check them against the derived
+       ones: edges_on_edge[e] must list EE(e) (the other edges of both cells
+       of e, n_edges_on_edge[e] = n_i + n_j - 2 of them, in any order) and
+       |w - w_derived| <= 1e-9 (1 + |w_derived|) for each, with
+       w_derived = -n_{e,i} n_{e',i} (R - 1/2), R the kite fractions
+       A_{i,v}/A_i summed counter-clockwise around the shared cell i from e'
+       to e.  A mismatch is LTS_EMESH naming the edge. */
+    int32_t max_edges2;
+    const int32_t *n_edges_on_edge;      /* [n_edges]                          */
+    const int32_t *edges_on_edge;        /* [n_edges][max_edges2]              */
+    const double *weights_on_edge;       /* [n_edges][max_edges2]              */
 } lts_mesh;
 
 typedef struct {
@@ -90,6 +104,9 @@ typedef struct {
     double h_min, h_max, u_absmax;
     int64_t n_nonfinite;  /* non-finite h or u values in the state              */
     int64_t steps;        /* coarse steps (LTS) or steps (RK3) taken            */
+    int64_t gate_fallbacks; /* surrogate steps the residual gate rejected and
+                               the plain LTS3 step recomputed (lts_sur_step),
+                               since the last lts_init_state                   */
 } lts_diag;
 
 /* Create a context on HIP device `device`, computing in `prec`.  hip_stream is

@@ -92,7 +92,7 @@ lts_status lts_sur_train(lts_sur *s, const int32_t *idx, int n_iters, float lr, 
 lts_status lts_sur_grad(lts_sur *s, int k, float *loss, float *grad);
 
 /* Raw node features of the current context state, [n_nodes][16] FP32:
-   0 h + b (minus a per-context constant in FP32 contexts), 1 b, 2 div u =
+   0 h + b (in every precision), 1 b, 2 div u =
    (1/A_i) sum_e n_{e,i} l_e u_e, 3 cell vorticity = sum over the cell's
    vertices of (kite area / A_i) times the vertex vorticity, 4 kinetic
    energy K_i (the K of the momentum equation), 5..8 region one-hot

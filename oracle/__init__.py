@@ -5,7 +5,11 @@ CPU-baseline leg may import this package.  The GPU library never does.
 
 The shared object is compiled in place with gcc on first use (and again when
 oracle.c or oracle.h is newer than it), with contraction of multiply-adds
-turned off so every operation rounds as written.
+turned off so every operation rounds as written.  A second build,
+liboracle_omp.so (-O3 -march=native -fopenmp, contraction still off), splits
+the per-element loops over host threads; it computes bitwise the same
+results and serves only to time the oracle on all host cores
+(Oracle(..., threads=n)).
 """
 from __future__ import annotations
 
@@ -19,27 +23,31 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_FLAGS = {_LIB: ["-O2", "-Wno-unknown-pragmas"],
+          _LIB_OMP: ["-O3", "-march=native", "-fopenmp"]}
+_libs = {}
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so next to its source; returns its path."""
-    stale = (not os.path.exists(_LIB)) or any(
-        os.path.getmtime(s) > os.path.getmtime(_LIB) for s in _SRC)
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile liboracle.so (or the threaded timing build liboracle_omp.so)
+    next to its source; returns its path."""
+    path = _LIB_OMP if omp else _LIB
+    stale = (not os.path.exists(path)) or any(
+        os.path.getmtime(s) > os.path.getmtime(path) for s in _SRC)
     if force or stale:
-        tmp = _LIB + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+        tmp = path + f".tmp{os.getpid()}"
+        cmd = ["gcc", *_FLAGS[path], "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
                "-Wall", "-o", tmp, _SRC[0], "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    lib = ctypes.CDLL(build())
+def _load(omp: bool = False):
+    if omp in _libs:
+        return _libs[omp]
+    lib = ctypes.CDLL(build(omp=omp))
     P = ctypes.c_void_p
     i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
     i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
@@ -65,7 +73,9 @@ def _load():
     lib.om_set_reading.argtypes = [ci]
     lib.om_get_reading.restype = ci
     lib.om_diagnostics.argtypes = [P, f64p, f64p, ctypes.POINTER(cd), ctypes.POINTER(cd)]
-    _lib = lib
+    lib.om_set_threads.argtypes = [ci]
+    lib.om_get_threads.restype = ci
+    _libs[omp] = lib
     return lib
 
 
@@ -106,8 +116,13 @@ def predict_coeffs(order: int, stage: int, k: int, M: int) -> np.ndarray:
 class Oracle:
     """FP64 reference for the TRiSK right-hand side and the time integrators."""
 
-    def __init__(self, mesh, gravity: float = 9.81):
-        lib = _load()
+    def __init__(self, mesh, gravity: float = 9.81, threads: int | None = None):
+        """threads: None for the single-threaded build; n > 0 for the threaded
+        timing build with n threads (bitwise the same results)."""
+        lib = _load(omp=threads is not None)
+        if threads is not None:
+            lib.om_set_threads(int(threads))
+        self.threads = lib.om_get_threads()
         self.mesh = mesh
         self.gravity = float(gravity)
         m = mesh

@@ -211,3 +211,17 @@ def loss_and_grad(p, G: Graph, X, th, tu):
     grads["W0"] = cache["X"].T @ dZ
     grads["b0"] = dZ.sum(axis=0)
     return loss, pack(grads)
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One step of Adam (Kingma and Ba, 2015, Algorithm 1) in FP64: the
+    biased moment estimates m <- b1 m + (1 - b1) g and v <- b2 v + (1 - b2) g^2,
+    their bias corrections m / (1 - b1^t) and v / (1 - b2^t) for step t >= 1,
+    and p <- p - lr m_hat / (sqrt(v_hat) + eps).  Returns (p, m, v)."""
+    p = np.asarray(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -11,6 +11,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Reading of the paper's garbled passages.  0 is the reading this oracle
    defends; the others reproduce the literal printed text and exist only so
@@ -20,6 +23,26 @@
      3: eq:weights with V_{i*} collected clockwise (read at om_create); the
         paper allows either direction and the tests show both agree. */
 static int g_reading = 0;
+
+/* Threads of the timing build (compiled with OpenMP: the per-element loops of
+   the right-hand side and of the stage updates are split over threads; each
+   element is still computed by the same operations in the same order, so the
+   results are bitwise those of the single-threaded build).  Without OpenMP
+   both calls do nothing and report one thread. */
+void om_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+int om_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 void om_set_reading(int r) { g_reading = r; }
 int om_get_reading(void) { return g_reading; }
 
@@ -175,6 +198,7 @@ int om_weights_on_edge(const om_ctx *c, int e, int32_t *ee, double *w) {
 /* [h]_{i->e} = 1/2 sum_{i in CE(e)} h_i;  F_e = [h]_{i->e} u_e. */
 static void thickness_flux(const om_ctx *c, const double *h, const double *u,
                            double *F) {
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < c->nE; ++e) {
         double he = 0.5 * (h[c->coe[2 * e]] + h[c->coe[2 * e + 1]]);
         F[e] = he * u[e];
@@ -183,6 +207,7 @@ static void thickness_flux(const om_ctx *c, const double *h, const double *u,
 
 /* K_i = 1/(4 A_i) sum_{e in EC(i)} l_e d_e u_e^2. */
 static void kinetic_energy(const om_ctx *c, const double *u, double *K) {
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < c->nC; ++i) {
         double s = 0.0;
         for (int j = 0; j < c->nEoC[i]; ++j) {
@@ -200,6 +225,7 @@ static void kinetic_energy(const om_ctx *c, const double *u, double *K) {
    thickness h_v = (1/A_v) sum_{i in CV(v)} A_{i,v} h_i. */
 static void vertex_pv(const om_ctx *c, const double *h, const double *u,
                       double *q, double *zeta) {
+    #pragma omp parallel for schedule(static)
     for (int v = 0; v < c->nV; ++v) {
         double circ = 0.0, hv = 0.0;
         for (int k = 0; k < 3; ++k) {
@@ -225,11 +251,13 @@ static void rhs_impl(const om_ctx *c, const double *h, const double *u,
     kinetic_energy(c, u, K);
     vertex_pv(c, h, u, q, zout);
     /* q~_e = 1/2 sum_{v in VE(e)} q_v (eq:discPV) */
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < c->nE; ++e)
         qt[e] = 0.5 * (q[c->voe[2 * e]] + q[c->voe[2 * e + 1]]);
 
     /* H_i = -[div F]_i = -(1/A_i) sum_{e in EC(i)} n_{e,i} l_e F_e */
     if (dh)
+        #pragma omp parallel for schedule(static)
         for (int i = 0; i < c->nC; ++i) {
             double s = 0.0;
             for (int j = 0; j < c->nEoC[i]; ++j) {
@@ -242,6 +270,7 @@ static void rhs_impl(const om_ctx *c, const double *h, const double *u,
     /* U_e = -F_perp_e[q]_{v->e} - [grad(g(h+b) + K)]_e, with
        F_perp_e[q] = sum_{e' in EE(e)} w_{e,e'} (l_{e'}/d_e) F_{e'} (q~_e+q~_{e'})/2
        (eq:discPV) and [grad phi]_e = (1/d_e) sum_{i in CE(e)} -n_{e,i} phi_i. */
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < c->nE; ++e) {
         double pv = 0.0, fp = 0.0;
         for (int k = c->ee_start[e]; k < c->ee_start[e + 1]; ++k) {
@@ -351,11 +380,15 @@ void om_ssprk_step(const om_ctx *c, int order, double *h, double *u, double dt) 
     double *dh = malloc(sizeof(double) * nC), *du = malloc(sizeof(double) * nE);
     /* stage 1 */
     om_rhs(c, h0, u0, dh, du);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i) h1[i] = h0[i] + dt * dh[i];
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e) u1[e] = u0[e] + dt * du[e];
     /* stage 2 */
     om_rhs(c, h1, u1, dh, du);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i) h2[i] = w_old * h0[i] + w_1 * h1[i] + w_1 * dt * dh[i];
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e) u2[e] = w_old * u0[e] + w_1 * u1[e] + w_1 * dt * du[e];
     if (order == 2) {
         memcpy(h, h2, sizeof(double) * nC);
@@ -363,8 +396,10 @@ void om_ssprk_step(const om_ctx *c, int order, double *h, double *u, double dt) 
     } else {
         /* stage 3 */
         om_rhs(c, h2, u2, dh, du);
+        #pragma omp parallel for schedule(static)
         for (int i = 0; i < nC; ++i)
             h[i] = h0[i] / 3.0 + 2.0 / 3.0 * h2[i] + 2.0 / 3.0 * dt * dh[i];
+        #pragma omp parallel for schedule(static)
         for (int e = 0; e < nE; ++e)
             u[e] = u0[e] / 3.0 + 2.0 / 3.0 * u2[e] + 2.0 / 3.0 * dt * du[e];
     }
@@ -386,12 +421,16 @@ void om_rk4_step(const om_ctx *c, double *h, double *u, double dt) {
             om_rhs(c, h, u, kh[0], ku[0]);
             continue;
         }
+        #pragma omp parallel for schedule(static)
         for (int i = 0; i < nC; ++i) ht[i] = h[i] + frac[s] * dt * kh[s - 1][i];
+        #pragma omp parallel for schedule(static)
         for (int e = 0; e < nE; ++e) ut[e] = u[e] + frac[s] * dt * ku[s - 1][e];
         om_rhs(c, ht, ut, kh[s], ku[s]);
     }
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i)
         h[i] += dt / 6.0 * (kh[0][i] + 2.0 * kh[1][i] + 2.0 * kh[2][i] + kh[3][i]);
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e)
         u[e] += dt / 6.0 * (ku[0][e] + 2.0 * ku[1][e] + 2.0 * ku[2][e] + ku[3][e]);
     free(ht); free(ut);
@@ -444,16 +483,20 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *creg,
 
     /* Step 1: first stage with dt on I1 u I2 u C (and underlined F for LTS3). */
     om_rhs(c, h0, u0, dh, du);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i)
         if (creg[i] != OM_F || (order == 3 && cfbar[i])) h1[i] = h0[i] + dt * dh[i];
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e)
         if (ereg[e] != OM_F || (order == 3 && efbar[e])) u1[e] = u0[e] + dt * du[e];
 
     /* Step 2: second stage with dt on C (LTS2) or I1 u I2 u C (LTS3). */
     om_rhs(c, h1, u1, dh, du);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i)
         if (creg[i] == OM_C || (order == 3 && creg[i] != OM_F))
             h2[i] = w_old * h0[i] + w_1 * h1[i] + w_1 * dt * dh[i];
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e)
         if (ereg[e] == OM_C || (order == 3 && ereg[e] != OM_F))
             u2[e] = w_old * u0[e] + w_1 * u1[e] + w_1 * dt * du[e];
@@ -478,19 +521,24 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *creg,
             /* Step 3.s.1: predict interface 1 at this fine stage. */
             double cf[3];
             om_lts_predict_coeffs(order, s, k, M, cf);
+            #pragma omp parallel for schedule(static)
             for (int i = 0; i < nC; ++i)
                 if (creg[i] == OM_I1)
                     hk[s][i] = cf[0] * h0[i] + cf[1] * h1[i] + cf[2] * h2[i];
+            #pragma omp parallel for schedule(static)
             for (int e = 0; e < nE; ++e)
                 if (ereg[e] == OM_I1)
                     uk[s][e] = cf[0] * u0[e] + cf[1] * u1[e] + cf[2] * u2[e];
             om_rhs(c, hk[s], uk[s], dh, du);
             /* Step 3.s.2: accumulate correction terms on I1 u I2. */
+            #pragma omp parallel for schedule(static)
             for (int i = 0; i < nC; ++i)
                 if (creg[i] == OM_I1 || creg[i] == OM_I2) Hacc[s][i] += dh[i];
+            #pragma omp parallel for schedule(static)
             for (int e = 0; e < nE; ++e)
                 if (ereg[e] == OM_I1 || ereg[e] == OM_I2) Uacc[s][e] += du[e];
             /* Step 3.s.3: SSPRK stage with dt/M on all fine cells and edges. */
+            #pragma omp parallel for schedule(static)
             for (int i = 0; i < nC; ++i) {
                 if (creg[i] != OM_F) continue;
                 if (s == 0)
@@ -502,6 +550,7 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *creg,
                 else
                     hk[0][i] = hk[0][i] / 3.0 + 2.0 / 3.0 * hk[lit2][i] + 2.0 / 3.0 * dfin * dh[i];
             }
+            #pragma omp parallel for schedule(static)
             for (int e = 0; e < nE; ++e) {
                 if (ereg[e] != OM_F) continue;
                 if (s == 0)
@@ -518,20 +567,24 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *creg,
 
     /* Step 4: coarse region (LTS3 third stage, LTS2 takes the second stage). */
     if (order == 3) om_rhs(c, h2, u2, dh, du);
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i)
         if (creg[i] == OM_C)
             h[i] = order == 3 ? h0[i] / 3.0 + 2.0 / 3.0 * h_s3[i] + 2.0 / 3.0 * dt * dh[i] : h2[i];
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e)
         if (ereg[e] == OM_C)
             u[e] = order == 3 ? u0[e] / 3.0 + 2.0 / 3.0 * u_s3[e] + 2.0 / 3.0 * dt * du[e] : u2[e];
 
     /* Step 5: interface correction; the fine region takes the last substep. */
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < nC; ++i) {
         if (creg[i] == OM_I1 || creg[i] == OM_I2)
             h[i] = h0[i] + delta * (th[0] * Hacc[0][i] + th[1] * Hacc[1][i] + th[2] * Hacc[2][i]);
         else if (creg[i] == OM_F)
             h[i] = hk[0][i];
     }
+    #pragma omp parallel for schedule(static)
     for (int e = 0; e < nE; ++e) {
         if (ereg[e] == OM_I1 || ereg[e] == OM_I2)
             u[e] = u0[e] + delta * (th[0] * Uacc[0][e] + th[1] * Uacc[1][e] + th[2] * Uacc[2][e]);

@@ -74,6 +74,65 @@ void free_device(lts_ctx* c) {
 }
 
 // ---------------------------------------------------------------- validation
+// Caller's edgesOnEdge / weightsOnEdge tables (optional) against the weights
+// of eq:weights derived from the kite areas: w_{e,e'} = -n_{e,i} n_{e',i}
+// (R - 1/2), R = kite fractions of cell i summed counter-clockwise from the
+// slot of e' to the slot of e (the vertex after slot j is vertices_on_cell[j]).
+lts_status check_weights(lts_ctx* c, const lts_mesh* m) {
+    const bool any = m->n_edges_on_edge || m->edges_on_edge || m->weights_on_edge;
+    if (!any) return LTS_OK;
+    if (!m->n_edges_on_edge || !m->edges_on_edge || !m->weights_on_edge || m->max_edges2 < 1)
+        return fail(c, LTS_EINVAL, "edges_on_edge tables: give all three with max_edges2 >= 1");
+    const int mx = m->max_edges, m2 = m->max_edges2;
+    auto kite = [&](int i, int v) {
+        for (int k = 0; k < 3; ++k)
+            if (m->cells_on_vertex[3 * v + k] == i) return m->kite_areas_on_vertex[3 * v + k];
+        return 0.0;
+    };
+    std::vector<int> ee;
+    std::vector<double> wd;
+    for (int e = 0; e < m->n_edges; ++e) {
+        ee.clear();
+        wd.clear();
+        for (int s = 0; s < 2; ++s) {
+            const int i = m->cells_on_edge[2 * e + s];
+            const int n = m->n_edges_on_cell[i];
+            const int32_t* eo = m->edges_on_cell + (size_t)i * mx;
+            const int32_t* vo = m->vertices_on_cell + (size_t)i * mx;
+            int b = 0;
+            while (b < n && eo[b] != e) ++b;
+            const double ne = m->cells_on_edge[2 * e] == i ? 1.0 : -1.0;
+            for (int a = 0; a < n; ++a) {
+                if (a == b) continue;
+                double R = 0.0;
+                for (int j = a; j != b; j = (j + 1) % n) R += kite(i, vo[j]) / m->area_cell[i];
+                const double na = m->cells_on_edge[2 * eo[a]] == i ? 1.0 : -1.0;
+                ee.push_back(eo[a]);
+                wd.push_back(-ne * na * (R - 0.5));
+            }
+        }
+        const int ne_e = m->n_edges_on_edge[e];
+        if (ne_e != (int)ee.size() || ne_e > m2)
+            return fail(c, LTS_EMESH, "n_edges_on_edge differs from n_i + n_j - 2 at edge " +
+                                          std::to_string(e));
+        for (int k = 0; k < ne_e; ++k) {
+            const int ep = m->edges_on_edge[(size_t)e * m2 + k];
+            const double w = m->weights_on_edge[(size_t)e * m2 + k];
+            const auto it = std::find(ee.begin(), ee.end(), ep);
+            if (it == ee.end())
+                return fail(c, LTS_EMESH, "edges_on_edge lists an edge outside EE(e) at edge " +
+                                              std::to_string(e));
+            const double d = wd[it - ee.begin()];
+            if (!(std::fabs(w - d) <= 1e-9 * (1.0 + std::fabs(d))))
+                return fail(c, LTS_EMESH, "weights_on_edge differs from the kite-area weights at edge " +
+                                              std::to_string(e) + " (given " + std::to_string(w) +
+                                              ", derived " + std::to_string(d) + ")");
+            ee[it - ee.begin()] = -1;  // each member once
+        }
+    }
+    return LTS_OK;
+}
+
 lts_status validate(lts_ctx* c, const lts_mesh* m) {
     const int nC = m->n_cells, nE = m->n_edges, nV = m->n_vertices, mx = m->max_edges;
     if (nC < 3 || nE < 3 || nV < 3 || mx < 3)
@@ -135,7 +194,7 @@ lts_status validate(lts_ctx* c, const lts_mesh* m) {
                 return fail(c, LTS_EMESH, "non-positive kite area");
         }
     }
-    return LTS_OK;
+    return check_weights(c, m);
 }
 
 // ---------------------------------------------------------------- regions
@@ -562,7 +621,9 @@ lts_status eval_rhs(lts_ctx* c, const double* h, const double* u, double* dh, do
     HIPCHK(c, hipMemcpyAsync(uu.data(), c->Cu, nE * L * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     from_device<T>(c, hh, uu, dh, du, false);
-    // eval_rhs clobbers the stage buffers: force the next step to re-capture
+    // the stage buffers B and C now hold the evaluation's input and output;
+    // a captured step graph stays valid, since every step writes them before
+    // it reads them
     return LTS_OK;
 }
 
@@ -857,6 +918,7 @@ lts_status lts_init_state(lts_ctx* c, const double* h, const double* u, double t
     c->nonfinite = false;
     c->t = t0;
     c->steps = 0;
+    c->gate_fallbacks = 0;
     return LTS_OK;
 }
 
@@ -932,6 +994,7 @@ lts_status lts_diagnostics(lts_ctx* c, lts_diag* out) {
     out->u_absmax = d[4];
     out->n_nonfinite = (int64_t)d[5];
     out->steps = c->steps;
+    out->gate_fallbacks = c->gate_fallbacks;
     if (d[6] != 0 || d[5] != 0) c->nonfinite = true;
     if (c->nonfinite) return fail(c, LTS_ENONFINITE, "a step produced non-finite values");
     return LTS_OK;

@@ -65,6 +65,7 @@ struct lts_ctx {
 
     double t = 0.0;
     int64_t steps = 0;
+    int64_t gate_fallbacks = 0;  // surrogate steps rejected by the gate
 
     // perturbation thickness form (FP32): state holds eta = h - href
     bool pert = false;

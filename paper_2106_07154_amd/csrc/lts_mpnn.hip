@@ -560,7 +560,10 @@ __global__ void k_features(DevMesh<T> m, const T* __restrict__ h, const T* __res
         vort += m.kf[o] * (circ / av);
     }
     float* r = raw + (size_t)i * kFeat;
-    r[0] = (float)(h[i] + m.beta[i]);
+    // h + b: in the perturbation form (href present) the state holds
+    // eta = h - href, so h + b = href + eta + b, summed in FP64
+    r[0] = m.href ? (float)((double)m.href[i] + (double)h[i] + (double)m.bot[i])
+                  : (float)(h[i] + m.beta[i]);
     r[1] = (float)m.bot[i];
     r[2] = (float)(div / m.area[i]);
     r[3] = (float)vort;

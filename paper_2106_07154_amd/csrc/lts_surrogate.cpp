@@ -349,6 +349,7 @@ lts_status sur_step_typed(lts_sur* s, double dt, int M, int n, double tau, int m
             c->steps += 1;
             s->backoff = 0;
         } else {
+            c->gate_fallbacks += 1;
             s->backoff = std::min(max_backoff, s->backoff ? 2 * s->backoff : 1);
             s->skip = s->backoff;
             SCHK(s, hipMemcpyAsync(c->Ah, s->Sh, c->nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));

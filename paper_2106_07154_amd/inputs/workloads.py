@@ -103,29 +103,54 @@ def ensemble_sizes(n_members=64, lo=1.0e4, hi=4.0e5, seed=ENS_SEED):
     return np.exp(rng.uniform(np.log(lo), np.log(hi), n_members)).astype(np.int64)
 
 
-def ensemble_member(j, n_cells, iters=10, seed=ENS_SEED) -> Workload:
-    """Member j: the variable-resolution planar family scaled to n_cells,
-    Lloyd-relaxed at least `iters` times and then two at a time until every
-    kite area is positive and no cell has more than 8 edges (at most 40
-    iterations); bump 5(1 + 0.2 z) m, sigma 40(1 + 0.1 z) km, centre jittered
-    by up to 50 km; M drawn from {2, 4, 8}."""
-    rng = np.random.default_rng(seed + j)
+# Members whose relaxed points are cached in data/ (written by
+# make_ensemble_points.py): two of each size class, one above 300k cells, M
+# covering {2, 4, 8}; the oracle-checked ensemble test uses them.
+ENS_CACHED = (20, 40, 24, 33, 62, 23)
+
+
+def _member_cache_path(j, n_cells, iters, seed):
+    return os.path.join(DATA, f"ens{j}_n{int(n_cells)}_s{seed}_i{iters}_u32.npy")
+
+
+def member_points(j, n_cells, iters=10, seed=ENS_SEED):
+    """Relaxed generator points of member j (Morton-sorted) and the Lloyd
+    iterations taken: n_cells seeded points of the variable-resolution
+    planar family, Lloyd-relaxed at least `iters` times and then two at a
+    time until every kite area is positive and no cell has more than 8 edges
+    (at most 40 iterations)."""
     L = vp.VR_DOMAIN
     p = vp.sample_points(int(n_cells), L, L, vp.vr_spacing_shape, seed + j)
     dens = lambda x, y: vp.vr_spacing_shape(x, y) ** -4.0
     done = 0
-    m = None
-    while m is None:
+    while True:
         for _ in range(iters if done == 0 else 2):
             p = vp.lloyd_step(p, L, L, dens)
             done += 1
+        ps = vp.morton_sort(p, L)
         try:
-            m = vp.periodic_voronoi_mesh(vp.morton_sort(p, L), L, L, f0=1.0e-4, name=f"member{j}")
-            if m.maxEdges > 8 and done < 40:
-                m = None
+            m = vp.periodic_voronoi_mesh(ps, L, L, f0=1.0e-4, name=f"member{j}")
+            if m.maxEdges <= 8 or done >= 40:
+                return ps, done
         except ValueError:
             if done >= 40:
                 raise
+
+
+def ensemble_member(j, n_cells, iters=10, seed=ENS_SEED) -> Workload:
+    """Member j: the variable-resolution planar family scaled to n_cells
+    (member_points; read from data/ when cached there as uint32 fixed-point
+    coordinates); bump 5(1 + 0.2 z) m, sigma 40(1 + 0.1 z) km, centre jittered
+    by up to 50 km; M drawn from {2, 4, 8}."""
+    rng = np.random.default_rng(seed + j)
+    L = vp.VR_DOMAIN
+    path = _member_cache_path(j, n_cells, iters, seed)
+    if os.path.exists(path):
+        q = np.load(path, allow_pickle=False)
+        p, done = q[:-1].astype(np.float64) * (L / 2.0 ** 32), int(q[-1, 0])
+    else:
+        p, done = member_points(j, n_cells, iters, seed)
+    m = vp.periodic_voronoi_mesh(p, L, L, f0=1.0e-4, name=f"member{j}")
     fm = (vp.vr_spacing_shape(m.xCell, m.yCell) < 0.9 * vp.VR_RATIO).astype(np.uint8)
     z = rng.standard_normal(2)
     cx, cy = L / 2 + rng.uniform(-5.0e4, 5.0e4, 2)

@@ -48,14 +48,17 @@ class _Mesh(ctypes.Structure):
             "n_edges_on_cell", "edges_on_cell", "cells_on_cell", "vertices_on_cell",
             "cells_on_edge", "vertices_on_edge", "edges_on_vertex", "cells_on_vertex",
             "kite_areas_on_vertex", "area_cell", "area_triangle", "dc_edge", "dv_edge",
-            "f_vertex", "bottom", "cell_xyz")]
+            "f_vertex", "bottom", "cell_xyz")] + [
+        ("max_edges2", ctypes.c_int32), ("n_edges_on_edge", ctypes.c_void_p),
+        ("edges_on_edge", ctypes.c_void_p), ("weights_on_edge", ctypes.c_void_p)]
 
 
 class _Diag(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("mass", ctypes.c_double),
                 ("energy", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("h_max", ctypes.c_double), ("u_absmax", ctypes.c_double),
-                ("n_nonfinite", ctypes.c_int64), ("steps", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("gate_fallbacks", ctypes.c_int64)]
 
 
 @dataclass
@@ -68,6 +71,7 @@ class Diag:
     u_absmax: float
     n_nonfinite: int
     steps: int
+    gate_fallbacks: int = 0
 
 
 _lib = None
@@ -186,8 +190,8 @@ class LTSContext:
 
     # ---------------------------------------------------------------- mesh
     def upload_mesh(self, mesh, fine_mask, n_if1: int = 2, n_if2: int = 2,
-                    gravity: float = 9.81, use_positions: bool = True):
-        m, keep = _mesh_struct(mesh, use_positions)
+                    gravity: float = 9.81, use_positions: bool = True, edge_weights=None):
+        m, keep = _mesh_struct(mesh, use_positions, edge_weights)
         fm = np.ascontiguousarray(fine_mask, np.uint8)
         self._check(self._lib.lts_upload_mesh(self._h, ctypes.byref(m), _ptr(fm), int(n_if1),
                                               int(n_if2), float(gravity)))
@@ -259,13 +263,14 @@ class LTSContext:
     def diagnostics(self) -> Diag:
         d = _Diag()
         self._check(self._lib.lts_diagnostics(self._h, ctypes.byref(d)))
-        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps)
+        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps,
+                    d.gate_fallbacks)
 
     def diagnostics_status(self):
         d = _Diag()
         st = self._lib.lts_diagnostics(self._h, ctypes.byref(d))
         return st, Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite,
-                        d.steps)
+                        d.steps, d.gate_fallbacks)
 
     # ---------------------------------------------------------------- timing
     def set_timing(self, enable: bool):
@@ -283,7 +288,10 @@ class LTSContext:
                 for i in range(k)}
 
 
-def _mesh_struct(mesh, use_positions=True):
+def _mesh_struct(mesh, use_positions=True, edge_weights=None):
+    """ctypes lts_mesh of a mesh object (MPAS field names).  edge_weights:
+    optional (n_edges_on_edge [nE], edges_on_edge [nE][maxE2],
+    weights_on_edge [nE][maxE2]) tables for the library to check."""
     i32 = lambda a: np.ascontiguousarray(a, np.int32)
     f64 = lambda a: np.ascontiguousarray(a, np.float64)
     arrs = dict(
@@ -298,6 +306,12 @@ def _mesh_struct(mesh, use_positions=True):
         z = mesh.zCell if getattr(mesh, "zCell", None) is not None else np.zeros(mesh.nCells)
         arrs["cell_xyz"] = f64(np.stack([mesh.xCell, mesh.yCell, z], 1))
     m = _Mesh(mesh.nCells, mesh.nEdges, mesh.nVertices, mesh.maxEdges)
+    if edge_weights is not None:
+        ne, ee, we = edge_weights
+        ee, we = i32(ee), f64(we)
+        assert ee.ndim == 2 and ee.shape == we.shape and ee.shape[0] == mesh.nEdges
+        arrs.update(n_edges_on_edge=i32(ne), edges_on_edge=ee, weights_on_edge=we)
+        m.max_edges2 = ee.shape[1]
     for k, v in arrs.items():
         setattr(m, k, _ptr(v))
     return m, arrs
@@ -306,7 +320,8 @@ def _mesh_struct(mesh, use_positions=True):
 PASS_NAMES = ["full", "step1", "step2", "step3", "step4"]
 
 
-def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = True):
+def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = True,
+         edge_weights=None):
     """Host-only lts_plan: labels, device ordering and pass ranges (no GPU)."""
     lib = load_library()
     if not hasattr(lib, "_plan_typed"):
@@ -315,7 +330,7 @@ def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = 
             [ctypes.c_char_p, ctypes.c_int]
         lib.lts_plan.restype = ctypes.c_int
         lib._plan_typed = True
-    m, keep = _mesh_struct(mesh, use_positions)
+    m, keep = _mesh_struct(mesh, use_positions, edge_weights)
     fm = np.ascontiguousarray(fine_mask, np.uint8)
     out = dict(cell_region=np.empty(mesh.nCells, np.int8), edge_region=np.empty(mesh.nEdges, np.int8),
                cell_fbar=np.empty(mesh.nCells, np.uint8), edge_fbar=np.empty(mesh.nEdges, np.uint8),
@@ -401,7 +416,8 @@ class Ensemble:
     def diagnostics(self, j) -> Diag:
         d = _Diag()
         self._check(self._lib.lts_ens_diagnostics(self._h, int(j), ctypes.byref(d)))
-        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps)
+        return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps,
+                    d.gate_fallbacks)
 
     def info(self):
         tuned = np.zeros(18, np.int32)

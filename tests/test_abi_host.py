@@ -198,3 +198,45 @@ def test_rejects_broken_meshes(lib, hex8):
     with pytest.raises(lts.LTSError) as ei:
         lts.plan(hex8, fm, 0, 2)
     assert ei.value.status == lts.LTS_ELABEL
+
+
+def _oracle_weight_tables(mesh):
+    o = Oracle(mesh)
+    n = np.array([o._lib.om_n_edges_on_edge(o._h, e) for e in range(mesh.nEdges)], np.int32)
+    m2 = int(n.max())
+    ee = np.full((mesh.nEdges, m2), -1, np.int32)
+    we = np.zeros((mesh.nEdges, m2))
+    for e in range(mesh.nEdges):
+        a, w = o.weights(e)
+        ee[e, :len(a)], we[e, :len(a)] = a, w
+    return n, ee, we
+
+
+def test_mpas_weight_tables_checked_against_derived(lib, irregular):
+    """Optional edgesOnEdge / weightsOnEdge tables (the oracle's eq:weights,
+    in a shuffled order per edge) pass the library's check against its own
+    kite-area weights; a perturbed weight, a wrong member and a wrong count
+    are LTS_EMESH naming the edge."""
+    m = irregular
+    fm = (np.arange(m.nCells) % 16 < 5).astype(np.uint8)
+    n, ee, we = _oracle_weight_tables(m)
+    rng = np.random.default_rng(4)
+    for e in range(m.nEdges):
+        p = rng.permutation(n[e])
+        ee[e, :n[e]], we[e, :n[e]] = ee[e, p], we[e, p]
+    lts.plan(m, fm, 1, 1, edge_weights=(n, ee, we))
+    bad = we.copy()
+    bad[17, 2] += 1e-6
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm, 1, 1, edge_weights=(n, ee, bad))
+    assert ei.value.status == lts.LTS_EMESH and "edge 17" in str(ei.value)
+    bad = ee.copy()
+    bad[5, 0] = (bad[5, 0] + 1) % m.nEdges if bad[5, 0] + 1 not in ee[5] else bad[5, 0] + 2
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm, 1, 1, edge_weights=(n, bad, we))
+    assert ei.value.status == lts.LTS_EMESH
+    badn = n.copy()
+    badn[9] -= 1
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm, 1, 1, edge_weights=(badn, ee, we))
+    assert ei.value.status == lts.LTS_EMESH and "edge 9" in str(ei.value)

@@ -150,3 +150,30 @@ def test_max_dt_search_finds_known_limits(capsys):
     assert md["M"] == 6 and md["coarse_s"] <= lim["coarse"]
     assert out["runs"]["lts3_fp64"]["M"] == 6
     assert out["value"] == 0.0 and out["paper_metrics"]["C_cf"] == round(120 / 50, 3)
+
+
+def test_horizon_steps_cover_the_fixed_time():
+    """Every time-to-solution run covers exactly the simulated time, whatever
+    its step factor (and whatever --steps), with no step above the asked one."""
+    for T in (3600.0, 1234.5):
+        for step in (21.4, 5.35, 5.35 / 4, 3600.0, 7.0):
+            n, s = bench.horizon_steps(T, step)
+            assert abs(n * s - T) <= 1e-9 * T and s <= step * (1 + 1e-12)
+            assert n == 1 or (n - 1) * step < T
+
+
+def test_oracle_baseline_sample_and_parity_state(hex16):
+    """The CPU-baseline helper times whole coarse steps of the oracle and hands
+    back the state after the first ones, equal to the plain oracle's."""
+    import numpy as np
+    from oracle import Oracle
+    from paper_2106_07154_amd.inputs.workloads import Workload
+    from paper_2106_07154_amd.inputs import igw_parameters, igw_state, strip_fine_mask
+    m = hex16
+    h0, u0 = igw_state(m, igw_parameters(m), 0.0)
+    w = Workload("hex16", m, strip_fine_mask(m, 6, 9, 1.0e4), h0, u0, 30.0, 4)
+    v, n, t, early, th = bench.oracle_baseline(w, m.nCells * 4, 2, 0.2, first_steps=2)
+    assert n >= 2 and v > 0 and th == 2
+    o = Oracle(m)
+    rh, ru = o.lts(h0, u0, 30.0, 4, o.regions(w.fine_mask, 2, 2), n=2)
+    assert np.array_equal(early[0], rh) and np.array_equal(early[1], ru)

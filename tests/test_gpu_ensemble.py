@@ -69,12 +69,15 @@ def test_ensemble_matches_members_alone(members, prec):
         assert rel_l2(gh, rh) <= tol and rel_l2(gu, ru) <= tol * 10
         d = ens.diagnostics(j)
         assert d.steps == 4 and d.n_nonfinite == 0
-    # one member against the oracle
-    m, fm, h, u, dt, M = members[2]
-    o = Oracle(m)
-    rh, ru = o.lts(h, u, dt, M, o.regions(fm, 2, 2), n=4)
-    gh, gu = ens.get_member(2)
-    assert rel_l2(gh, rh) < (1e-12 if prec == "fp64" else 1e-5)
+    # every member against the FP64 oracle (h and u)
+    tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        o = Oracle(m)
+        rh, ru = o.lts(h, u, dt, M, o.regions(fm, 2, 2), n=4)
+        gh, gu = ens.get_member(j)
+        eh, eu = rel_l2(gh, rh), rel_l2(gu, ru)
+        say("member", j, m.nCells, "M", M, "oracle rel L2 h", eh, "u", eu)
+        assert eh < tol_h and eu < tol_u, j
     ens.close()
 
 
@@ -86,4 +89,50 @@ def test_ensemble_errors(hex8):
     with pytest.raises(lts.LTSError) as ei:
         ens.build()
     assert ei.value.status == lts.LTS_ESTATE
+    ens.close()
+
+
+@pytest.fixture(scope="module")
+def config4_members():
+    """Six members of the 64-member ensemble workload, built by its own
+    generator (seed 7000 + j) from the cached relaxed points: two of each size
+    class (< 30k, < 120k, larger), one of 352k cells, M in {2, 4, 8}."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07154_amd.inputs import workloads
+    sizes = workloads.ensemble_sizes(64)
+    return [workloads.ensemble_member(j, int(sizes[j])) for j in workloads.ENS_CACHED]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config4_members_match_oracle(config4_members, prec):
+    ws = config4_members
+    say("config-4 members", prec, [(w.name, w.mesh.nCells, w.M) for w in ws])
+    assert {w.M for w in ws} == {2, 4, 8}
+    n = [w.mesh.nCells for w in ws]
+    assert min(n) < 30_000 and any(30_000 <= x < 120_000 for x in n) and max(n) >= 300_000
+    ens = lts.Ensemble(0, prec)
+    for w in ws:
+        ens.add_member(w.mesh, w.fine_mask, w.dt_coarse, w.M, w.n_if1, w.n_if2, w.gravity)
+    for j, w in enumerate(ws):
+        ens.init_member(j, w.h0, w.u0)
+    ens.build(autotune=False)
+    ens.step(2)
+    tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
+    for j, w in enumerate(ws):
+        m = w.mesh
+        o = Oracle(m, w.gravity)
+        rh, ru = o.lts(w.h0, w.u0, w.dt_coarse, w.M, o.regions(w.fine_mask, w.n_if1, w.n_if2),
+                       n=2)
+        gh, gu = ens.get_member(j)
+        eh = math.sqrt((m.areaCell * (gh - rh) ** 2).sum() / (m.areaCell * rh ** 2).sum())
+        eu = rel_l2(gu, ru)
+        ep = math.sqrt((m.areaCell * (gh - rh) ** 2).sum() /
+                       (m.areaCell * (rh - w.extra["H"]) ** 2).sum())
+        say(w.name, m.nCells, "M", w.M, "rel L2 h", eh, "u", eu, "h - H", ep)
+        assert eh < tol_h and eu < tol_u, w.name
+        d = ens.diagnostics(j)
+        assert d.steps == 2 and d.n_nonfinite == 0
     ens.close()

@@ -16,6 +16,13 @@ from paper_2106_07154_amd.inputs import workloads
 
 pytestmark = pytest.mark.gpu
 
+# FP32 LTS3 on the 1.6M-cell sphere against the FP64 oracle after 2 coarse
+# steps, per field: measured values times about 4 (stated in the design doc's
+# tolerance section)
+FP32_SPHERE_ETA_TOL = 1e-5
+FP32_SPHERE_MASS_TOL = 1e-8
+FP32_SPHERE_ENERGY_TOL = 1e-6
+
 
 def say(*a):
     print("[gpu-case]", *a, flush=True)
@@ -127,6 +134,7 @@ def full():
     o = Oracle(w.mesh, w.gravity)
     R = o.regions(w.fine_mask, w.n_if1, w.n_if2)
     rh, ru = o.lts(w.h0, w.u0, w.dt_coarse, w.M, R, n=2)
+    w.extra["oracle_diag"] = o.diagnostics(rh, ru)
     return w, rh, ru
 
 
@@ -141,6 +149,17 @@ def test_full_sphere_lts3(full, prec, tol_h, tol_u):
     m = w.mesh
     eh = rel_l2(gh, rh, m.areaCell)
     eu = rel_l2(gu, ru, m.dvEdge * m.dcEdge)
-    say("rel L2 h", eh, "u", eu)
+    # surface anomaly eta = h + b - mean(h + b) (the dynamic part of h)
+    Hs = float((m.areaCell * (rh + m.bottom)).sum() / m.areaCell.sum())
+    ea = rel_l2(gh + m.bottom - Hs, rh + m.bottom - Hs, m.areaCell)
+    d = c.diagnostics()
+    m_ref, e_ref = w.extra["oracle_diag"]
+    em, ee = abs(d.mass - m_ref) / m_ref, abs(d.energy - e_ref) / abs(e_ref)
+    say("rel L2 h", eh, "eta", ea, "u", eu, "mass", em, "energy", ee)
     assert eh < tol_h and eu < tol_u
+    if prec == "fp32":
+        assert ea < FP32_SPHERE_ETA_TOL and em < FP32_SPHERE_MASS_TOL
+        assert ee < FP32_SPHERE_ENERGY_TOL
+    else:
+        assert ea < 1e-11 and em < 1e-13 and ee < 1e-12
     c.close()

@@ -168,6 +168,33 @@ def test_node_set_and_features(lloyd_setup):
         assert np.all(err <= 2 ** -23 * np.abs(ref[:, f]) + 1e-6 * scale), f
 
 
+def test_fp32_features_follow_the_state(lloyd_mesh):
+    """FP32 contexts store eta = h - href with href taken from the mean
+    surface at each lts_init_state: the features must still be those of h
+    (feature 0 is h + b, not h + b minus that surface), for two initial
+    states whose mean surfaces differ by 30 m."""
+    m, fm, h, u = _lloyd_case(lloyd_mesh)
+    say("fp32 surrogate features", m.nCells)
+    o = Oracle(m)
+    reg = o.regions(fm, 2, 2)
+    ctx = lts.LTSContext(0, "fp32")
+    ctx.upload_mesh(m, fm, 2, 2)
+    for shift in (0.0, 30.0):
+        ctx.init_state(h + shift, u)
+        sur = lts.Surrogate(ctx, seed=1)
+        nodes, _ = sur.node_map()
+        raw = sur.features()
+        ref = mpnn.raw_features(m, o, reg, h + shift, u, nodes)
+        for f in range(16):
+            scale = max(np.abs(ref[:, f]).max(), 1e-30)
+            err = np.abs(raw[:, f] - ref[:, f])
+            tol = 2 ** -22 * np.abs(ref[:, f]) + (1e-5 * scale if 2 <= f <= 4 else 0.0)
+            say("feature", f, "max err", float(err.max()), "scale", scale)
+            assert np.all(err <= tol + 1e-30), (shift, f)
+        sur.close()
+    ctx.close()
+
+
 def test_forward_parity(lloyd_setup):
     S = lloyd_setup
     sur, G = S["sur"], S["G"]
@@ -214,6 +241,40 @@ def test_gradient_parity(lloyd_setup):
         say("grad", name, e)
         assert e < 4e-2, name
         off += n
+
+
+def test_adam_update_matches_oracle(lloyd_setup):
+    """Two Adam steps of lts_sur_train against the FP64 Adam of oracle/mpnn.py
+    fed the library's own gradients (lts_sur_grad runs the same deterministic
+    kernels as the training step) and its FP32 hyperparameters.  Each step
+    rounds once to FP32 and carries a few FP32 roundings in its update
+    term: |p - p_ref| <= 2^-23 |p_ref| + 1e-5 |p_ref - p_prev| + 1e-12."""
+    S = lloyd_setup
+    sur, ctx = S["sur"], S["ctx"]
+    say("surrogate adam parity")
+    if sur.n_samples == 0:
+        dt = 0.3 * 3.0e3 / math.sqrt(9.81 * 500.0) * 4
+        ctx.init_state(S["h"], S["u"])
+        sur.record(dt, 4, 1)
+    ref_raw = mpnn.raw_features(S["m"], S["o"], S["reg"], S["h"], S["u"], S["G"].nodes)
+    sur.set_norm(_norm_from(ref_raw, np.ones(3), np.ones(3)))
+    p0 = _test_params(13).astype(np.float32)
+    sur.set_params(p0)                      # also clears the Adam state
+    lr = 3e-3
+    b1, b2, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-8))
+    m = v = np.zeros(p0.size)
+    prev = p0.astype(np.float64)
+    for t in (1, 2):
+        _, g = sur.grad(0)
+        sur.train(np.array([0], np.int32), lr=lr)
+        p = sur.get_params().astype(np.float64)
+        want, m, v = mpnn.adam_step(prev, g, m, v, t, float(np.float32(lr)), b1, b2, eps)
+        err = np.abs(p - want)
+        bound = 2.0 ** -23 * np.abs(want) + 1e-5 * np.abs(want - prev) + 1e-12
+        say("adam step", t, "max err/bound", float((err / bound).max()),
+            "moved", int(np.count_nonzero(p != prev)))
+        assert np.all(err <= bound), t
+        prev = p
 
 
 # --------------------------------------------------------- step and the gate

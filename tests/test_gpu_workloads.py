@@ -13,6 +13,13 @@ from paper_2106_07154_amd.inputs import workloads
 
 pytestmark = pytest.mark.gpu
 
+# FP32 against the FP64 oracle after 3 coarse steps, per field: measured
+# values times about 4 (the measured figures are stated in the design doc's
+# tolerance section)
+FP32_VR_PERT_TOL = 2e-5
+FP32_VR_MASS_TOL = 1e-8
+FP32_VR_ENERGY_TOL = 1e-6
+
 
 def say(*a):
     print("[gpu-case]", *a, flush=True)
@@ -82,8 +89,15 @@ def test_vr200k_lts3_fp32(vr):
     rh, ru = o.lts(h, u, w.dt_coarse, w.M, R, n=3)
     m = w.mesh
     eh, eu = rel_l2(gh, rh, m.areaCell), rel_l2(gu, ru, m.dvEdge * m.dcEdge)
-    say("fp32 errors", eh, eu, "perturbation", rel_l2(gh - 500.0, rh - 500.0, m.areaCell))
+    # per field: the height perturbation h - H (H = 500 m at rest), u, mass
+    # and energy against the FP64 oracle
+    ep = rel_l2(gh - 500.0, rh - 500.0, m.areaCell)
+    d = c.diagnostics()
+    m_ref, e_ref = o.diagnostics(rh, ru)
+    em, ee = abs(d.mass - m_ref) / m_ref, abs(d.energy - e_ref) / abs(e_ref)
+    say("fp32 errors h", eh, "h-H", ep, "u", eu, "mass", em, "energy", ee)
     assert eh < 1e-5 and eu < 1e-5
+    assert ep < FP32_VR_PERT_TOL and em < FP32_VR_MASS_TOL and ee < FP32_VR_ENERGY_TOL
     c.close()
 
 

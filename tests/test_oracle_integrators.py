@@ -285,3 +285,21 @@ def test_lts_step2_ignores_interior_fine_values(igw_case):
     keep_e = R.edge != om.F
     assert np.array_equal(a_h[keep_c], b_h[keep_c])
     assert np.array_equal(a_u[keep_e], b_u[keep_e])
+
+
+def test_threaded_timing_build_is_bitwise_identical(irregular):
+    """The all-core timing build of the oracle (OpenMP over per-element loops,
+    -O3 -march=native, contraction off) computes exactly what the plain build
+    computes: each element's operations and their order are unchanged."""
+    from paper_2106_07154_amd.inputs import random_state
+    m = irregular
+    o1 = Oracle(m)
+    o4 = Oracle(m, threads=4)
+    assert o1.threads == 1 and o4.threads == 4
+    h, u = random_state(m, 3, H=100.0, amp_h=1.0, amp_u=0.5)
+    fm = (np.arange(m.nCells) % 16 < 5).astype(np.uint8)
+    R = o1.regions(fm, 1, 1)
+    for fn in (lambda o: o.rhs(h, u), lambda o: o.lts(h, u, 30.0, 4, R, n=2),
+               lambda o: o.ssprk(h, u, 20.0, n=2), lambda o: o.rk4(h, u, 20.0, n=2)):
+        a, b = fn(o1), fn(o4)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -160,3 +160,37 @@ def test_feature_sums_telescope(irregular):
     assert abs(np.sum(m.areaCell * raw[:, 2])) <= 1e-12 * scale
     scale = np.sum(m.areaCell * np.abs(raw[:, 3]))
     assert abs(np.sum(m.areaCell * raw[:, 3])) <= 1e-12 * scale
+
+
+def test_adam_first_step_closed_form():
+    """Bias-corrected first step: m_hat = g and v_hat = g^2, so every
+    parameter moves by -lr g / (|g| + eps) whatever the scale of g."""
+    rng = np.random.default_rng(3)
+    p0 = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-6, 3, 50)
+    lr, eps = 1e-3, 1e-8
+    p1, m1, v1 = mpnn.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr, eps=eps)
+    np.testing.assert_allclose(p1 - p0, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_constant_gradient_and_sign_flip():
+    """A constant gradient keeps m_hat = g and v_hat = g^2 at every step
+    (the bias corrections undo the geometric sums exactly), so each step is
+    the first step's.  Gradients +1 then -1 with (b1, b2) = (0.9, 0.999):
+    m = -0.01, v = 0.001999, m_hat = -1/19, v_hat = 1, a step of
+    +lr / (19 (1 + eps))."""
+    lr, eps = 2e-3, 1e-8
+    p, m, v = np.array([0.5]), np.zeros(1), np.zeros(1)
+    for t in range(1, 6):
+        q, m, v = mpnn.adam_step(p, np.array([-3.0]), m, v, t, lr, eps=eps)
+        np.testing.assert_allclose(q - p, lr * 3.0 / (3.0 + eps), rtol=1e-9)
+        p = q
+    p, m, v = mpnn.adam_step(np.array([0.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr,
+                             eps=eps)
+    np.testing.assert_allclose(p, -lr / (1.0 + eps), rtol=1e-14)
+    p2, m, v = mpnn.adam_step(p, np.array([-1.0]), m, v, 2, lr, eps=eps)
+    np.testing.assert_allclose(m, -0.01, rtol=1e-12)
+    np.testing.assert_allclose(v, 0.001999, rtol=1e-12)
+    np.testing.assert_allclose(p2 - p, lr / (19.0 * (1.0 + eps)), rtol=1e-9)

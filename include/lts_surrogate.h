@@ -147,6 +147,30 @@ lts_status lts_nn_gemm_bf16_device(const uint16_t *A, int N, int K, const uint16
                                    const float *bias, float *Y_f32, uint16_t *Y_bf16,
                                    void *stream);
 
+/* lts_nn_gemm_tn_bf16_device_noalloc: for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving or training
+   loops, harnesses that forbid hipMalloc).  Computes the same product as
+   lts_nn_gemm_tn_bf16, P [K x 64] FP32 = A^T D with A [N x K] and D [N x 64]
+   BF16 bit patterns (K = 16, 32, ..., 128), on device buffers owned by the
+   caller, enqueued on `stream` (a hipStream_t of the current device; NULL:
+   the null stream) without synchronising.  It calls no hipMalloc, hipFree or
+   other allocating routine: the per-block partial sums go to a fixed 16 MiB
+   device array inside the library (one copy per GPU, held until the process
+   ends), whose address is looked up once per device on the first call made
+   with that device current.  N may be at most
+   lts_nn_gemm_tn_noalloc_max_rows(K) = 512 * floor(2^24 / (256 K)) rows
+   (262,144 at K = 128, 2,097,152 at K = 16); larger N, bad K or a missing
+   operand give LTS_EINVAL and enqueue nothing; a failed launch LTS_EDEVICE.
+   N = 0 writes zeros to P.  The result is bitwise that of
+   lts_nn_gemm_tn_bf16 (same kernels, same row partition).  Every call on one
+   GPU shares that GPU's array: calls that overlap in time on one GPU (other
+   streams, other host threads) race and give undefined results; calls
+   ordered on one stream do not.  lts_nn_gemm_tn_noalloc_max_rows returns 0
+   for an unsupported K. */
+lts_status lts_nn_gemm_tn_bf16_device_noalloc(const uint16_t *A, int N, int K, const uint16_t *D,
+                                              float *P, void *stream);
+long long lts_nn_gemm_tn_noalloc_max_rows(int K);
+
 #ifdef __cplusplus
 }
 #endif

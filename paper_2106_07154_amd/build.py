@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblts.so")
 SOURCES = [os.path.join(CSRC, n) for n in ("lts_api.cpp", "lts_ensemble.cpp", "lts_surrogate.cpp",
-                                             "lts_kernels.hip", "lts_mpnn.hip")]
+                                             "lts_kernels.hip", "lts_mpnn.hip",
+                                             "lts_noalloc.hip")]
 HEADERS = [os.path.join(CSRC, "lts_internal.h"), os.path.join(CSRC, "lts_host.h"),
            os.path.join(CSRC, "lts_mpnn.h"), os.path.join(ROOT, "include", "lts.h"),
            os.path.join(ROOT, "include", "lts_surrogate.h")]

@@ -16,6 +16,7 @@ namespace nn {
 constexpr int kFeat = 16;    // padded input width (first GEMM K)
 constexpr int kHid = 64;     // hidden width
 constexpr int kRawFeat = 9;  // used input columns: 5 physical + 4 region one-hot
+constexpr int kReduceRows = 512;  // rows per block of the reductions over nodes
 
 // Y = act(A W + bias): A [N x K] BF16 stride lda (K % 16 == 0, K <= 128),
 // W [K x 64] BF16; out_bf (stride ldo, relu if relu != 0) and/or out_f

@@ -25,7 +25,7 @@ constexpr int LAYER = 128 * 64 + 64;
 constexpr int OFF_WH = OFF_L1 + kLayers * LAYER, OFF_WU = OFF_WH + 64, OFF_BH = OFF_WU + 64;
 constexpr int N_PARAMS = OFF_BH + 1;
 constexpr int N_WBF = 16 * 64 + kLayers * 128 * 64;
-constexpr int RPB = 512;  // rows per block of the reductions over nodes
+constexpr int RPB = nn::kReduceRows;
 
 inline int off_w(int l) { return l == 0 ? OFF_W0 : OFF_L1 + (l - 1) * LAYER; }
 inline int off_b(int l) { return l == 0 ? OFF_B0 : OFF_L1 + (l - 1) * LAYER + 128 * 64; }

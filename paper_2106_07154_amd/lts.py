@@ -32,7 +32,8 @@ EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_get_regions"
             "lts_sur_normalize", "lts_sur_set_norm", "lts_sur_get_norm", "lts_sur_get_params",
             "lts_sur_set_params", "lts_sur_train", "lts_sur_grad", "lts_sur_features",
             "lts_sur_predict", "lts_sur_step", "lts_sur_last_error", "lts_sur_destroy",
-            "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16", "lts_nn_gemm_bf16_device"]
+            "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16", "lts_nn_gemm_bf16_device",
+            "lts_nn_gemm_tn_bf16_device_noalloc", "lts_nn_gemm_tn_noalloc_max_rows"]
 
 
 class LTSError(RuntimeError):
@@ -600,3 +601,36 @@ def nn_gemm_tn_bf16(A_bits, D_bits, device: int = 0):
     if st != LTS_OK:
         raise LTSError(st, "lts_nn_gemm_tn_bf16")
     return P
+
+
+def nn_gemm_tn_noalloc_max_rows(K: int) -> int:
+    """Largest N the allocation-free weight-gradient product accepts at K."""
+    lib = load_library()
+    lib.lts_nn_gemm_tn_noalloc_max_rows.argtypes = [ctypes.c_int]
+    lib.lts_nn_gemm_tn_noalloc_max_rows.restype = ctypes.c_longlong
+    return int(lib.lts_nn_gemm_tn_noalloc_max_rows(int(K)))
+
+
+def nn_gemm_tn_bf16_device_noalloc(A, D, P, stream=None):
+    """P = A^T D on torch device tensors through the entry point that
+    allocates nothing: A [N x K] and D [N x 64] int16/uint16 BF16 bit
+    patterns, P [K x 64] float32, on `stream` (torch stream or raw handle;
+    None: the null stream).  No copies, no synchronisation."""
+    lib = load_library()
+    if not hasattr(lib, "_gemm_tn_noalloc_typed"):
+        Pv = ctypes.c_void_p
+        lib.lts_nn_gemm_tn_bf16_device_noalloc.argtypes = [Pv, ctypes.c_int, ctypes.c_int, Pv,
+                                                           Pv, Pv]
+        lib.lts_nn_gemm_tn_bf16_device_noalloc.restype = ctypes.c_int
+        lib._gemm_tn_noalloc_typed = True
+    N, K = A.shape
+    assert tuple(D.shape) == (N, 64) and tuple(P.shape) == (K, 64)
+    assert A.is_contiguous() and D.is_contiguous() and P.is_contiguous()
+    assert A.element_size() == 2 and D.element_size() == 2 and P.element_size() == 4
+    sp = getattr(stream, "cuda_stream", stream)
+    st = lib.lts_nn_gemm_tn_bf16_device_noalloc(
+        ctypes.c_void_p(A.data_ptr()) if N else None, N, K,
+        ctypes.c_void_p(D.data_ptr()) if N else None, ctypes.c_void_p(P.data_ptr()),
+        None if sp is None else ctypes.c_void_p(sp))
+    if st != LTS_OK:
+        raise LTSError(st, "lts_nn_gemm_tn_bf16_device_noalloc")

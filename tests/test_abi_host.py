@@ -29,7 +29,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     import glob
     text = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
-    decl = re.compile(r"^(?:lts_status|void|int|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
+    decl = re.compile(r"^(?:lts_status|void|int|long long|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
                       re.M)
     declared = sorted(set(decl.findall(text)))
     assert len(declared) >= 15
@@ -49,7 +49,7 @@ def test_headers_are_c_and_link_from_c(lib, tmp_path):
     if gcc is None:
         pytest.skip("no gcc")
     text = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
-    decl = re.compile(r"^(?:lts_status|void|int|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
+    decl = re.compile(r"^(?:lts_status|void|int|long long|const char\s*\*)\s*\*?\s*(lts_[a-z0-9_]+)\s*\(",
                       re.M)
     names = sorted(set(decl.findall(text)))
     src = tmp_path / "abi.c"

@@ -321,22 +321,32 @@ double mean_surface(const lts_ctx* c, const std::vector<double>& h) {
 template <typename T>
 lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     const int nC = c->nC, nE = c->nE, nV = c->nV;
-    const int mx = padded_slots(c->maxE);  // slot tables padded to the kernel's slot count
     const int* cinv = c->cinv.data();
     const int* einv = c->einv.data();
     const int* vinv = c->vinv.data();
-    std::vector<int32_t> nEoC(nC), eoc((size_t)mx * nC, 0), coc((size_t)mx * nC, 0),
-        voc((size_t)mx * nC, 0);
-    std::vector<double> nl((size_t)mx * nC, 0), nd((size_t)mx * nC, 0), kc((size_t)mx * nC, 0),
-        kf((size_t)mx * nC, 0), sb((size_t)mx * nC, 0), sn(nC), area(nC), rarea(nC), bot(nC);
+    // compact slot tables: cell ni's slots start at cso[ni].x
+    std::vector<int32_t> nEoC(nC), cso(2 * (size_t)nC);
+    size_t nslots = 0;
+    for (int ni = 0; ni < nC; ++ni) {
+        const int n = m->n_edges_on_cell[c->cperm[ni]];
+        nEoC[ni] = n;
+        cso[2 * (size_t)ni] = (int32_t)nslots;
+        cso[2 * (size_t)ni + 1] = n;
+        nslots += n;
+    }
+    if (nslots > (size_t)INT32_MAX) return fail(c, LTS_EMESH, "more than 2^31 edge slots");
+    std::vector<int32_t> eoc(nslots), coc(nslots), voc(nslots);
+    std::vector<double> nl(nslots), nd(nslots), kc(nslots), kf(nslots), sb(nslots), sn(nC),
+        area(nC), rarea(nC), bot(nC);
     for (int ni = 0; ni < nC; ++ni) {
         const int i = c->cperm[ni];
-        const int n = m->n_edges_on_cell[i];
-        nEoC[ni] = n;
+        const int n = nEoC[ni];
+        const size_t o0 = (size_t)cso[2 * (size_t)ni];
         area[ni] = m->area_cell[i];
         bot[ni] = m->bottom[i];
+        double S = 0.0;  // counter-clockwise prefix sums of the kite fractions (FP64)
         for (int j = 0; j < n; ++j) {
-            const size_t o = (size_t)ni * mx + j;
+            const size_t o = o0 + j;
             const int e = m->edges_on_cell[(size_t)i * m->max_edges + j];
             const int v = m->vertices_on_cell[(size_t)i * m->max_edges + j];
             eoc[o] = einv[e];
@@ -350,19 +360,8 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
             for (int k = 0; k < 3; ++k)
                 if (m->cells_on_vertex[3 * v + k] == i) kite = m->kite_areas_on_vertex[3 * v + k];
             kf[o] = kite / m->area_cell[i];
-        }
-        // padding slots: repeat the last real slot's indices, zero coefficients
-        for (int j = n; j < mx; ++j) {
-            const size_t o = (size_t)ni * mx + j, ol = (size_t)ni * mx + n - 1;
-            eoc[o] = eoc[ol];
-            coc[o] = coc[ol];
-            voc[o] = voc[ol];
-        }
-        // counter-clockwise prefix sums of the kite fractions (FP64)
-        double S = 0.0;
-        for (int j = 0; j < mx; ++j) {
-            sb[(size_t)ni * mx + j] = S;
-            S += kf[(size_t)ni * mx + j];
+            sb[o] = S;
+            S += kf[o];
         }
         sn[ni] = S;
         rarea[ni] = 1.0 / m->area_cell[i];
@@ -390,6 +389,11 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     dm->maxE = c->maxE;
     lts_status s;
     if ((s = upload_vec<int32_t>(c, &dm->nEoC, nEoC))) return s;
+    {
+        const int32_t* p = nullptr;
+        if ((s = upload_vec<int32_t>(c, &p, cso))) return s;
+        dm->cso = reinterpret_cast<const int2*>(p);
+    }
     if ((s = upload_vec<int32_t>(c, &dm->eoc, eoc))) return s;
     if ((s = upload_vec<int32_t>(c, &dm->coc, coc))) return s;
     if ((s = upload_vec<int32_t>(c, &dm->voc, voc))) return s;
@@ -465,6 +469,67 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
 }
 
 // ---------------------------------------------------------------- plans
+// Kernel ranges of one pass with target cells [ct_lo, ct_hi) and target edges
+// [et_lo, et_hi) (device numbering): the cell kernel covers the targets and
+// both cells of every target edge, the vertex kernel every vertex of those
+// cells; plus the counts of unique elements the kernels gather.
+PassPlan plan_cover(const lts_ctx* c, const lts_mesh* m, int ct_lo, int ct_hi, int et_lo,
+                    int et_hi) {
+    const int nC = c->nC, nE = c->nE;
+    PassPlan P;
+    P.ct_lo = ct_lo;
+    P.ct_hi = ct_hi;
+    P.et_lo = et_lo;
+    P.et_hi = et_hi;
+    int lo = P.ct_lo, hi = P.ct_hi;
+    if (P.ct_hi <= P.ct_lo) { lo = nC; hi = 0; }
+    for (int ne = P.et_lo; ne < P.et_hi; ++ne) {
+        const int e = c->eperm[ne];
+        for (int s = 0; s < 2; ++s) {
+            const int ci = c->cinv[m->cells_on_edge[2 * e + s]];
+            lo = std::min(lo, ci);
+            hi = std::max(hi, ci + 1);
+        }
+    }
+    if (hi <= lo) { lo = hi = 0; }
+    P.c_lo = lo;
+    P.c_hi = hi;
+    int vlo = c->nV, vhi = 0;
+    std::vector<char> useu(nE, 0), useh(nC, 0), useq(c->nV, 0);
+    long slots = 0;
+    for (int ni = lo; ni < hi; ++ni) {
+        const int i = c->cperm[ni];
+        useh[ni] = 1;
+        for (int j = 0; j < m->n_edges_on_cell[i]; ++j) {
+            const int v = c->vinv[m->vertices_on_cell[(size_t)i * m->max_edges + j]];
+            vlo = std::min(vlo, v);
+            vhi = std::max(vhi, v + 1);
+            useq[v] = 1;
+            useu[c->einv[m->edges_on_cell[(size_t)i * m->max_edges + j]]] = 1;
+            useh[c->cinv[m->cells_on_cell[(size_t)i * m->max_edges + j]]] = 1;
+            ++slots;
+        }
+    }
+    if (vhi <= vlo) { vlo = vhi = 0; }
+    P.v_lo = vlo;
+    P.v_hi = vhi;
+    P.c_uniq_h = std::count(useh.begin(), useh.end(), 1);
+    P.c_uniq_u = std::count(useu.begin(), useu.end(), 1);
+    P.c_uniq_q = std::count(useq.begin(), useq.end(), 1);
+    P.c_slots = slots;
+    std::vector<char> vu(nE, 0), vh(nC, 0);
+    for (int nv = vlo; nv < vhi; ++nv) {
+        const int v = c->vperm[nv];
+        for (int k = 0; k < 3; ++k) {
+            vu[c->einv[m->edges_on_vertex[3 * v + k]]] = 1;
+            vh[c->cinv[m->cells_on_vertex[3 * v + k]]] = 1;
+        }
+    }
+    P.v_uniq_u = std::count(vu.begin(), vu.end(), 1);
+    P.v_uniq_h = std::count(vh.begin(), vh.end(), 1);
+    return P;
+}
+
 void make_plans(lts_ctx* c, const lts_mesh* m) {
     const int nC = c->nC, nE = c->nE;
     const int* cb = c->cb;
@@ -477,60 +542,11 @@ void make_plans(lts_ctx* c, const lts_mesh* m) {
         {0, cb[5], 0, eb[4]},      // STEP3: F, I (fine edges, I edges)
         {cb[5], nC, eb[4], nE},    // STEP4: C
     };
-    // new-numbering connectivity needed for coverage
-    for (int p = 0; p < P_N; ++p) {
-        PassPlan& P = c->plan[p];
-        P.ct_lo = targets[p].ct_lo;
-        P.ct_hi = targets[p].ct_hi;
-        P.et_lo = targets[p].et_lo;
-        P.et_hi = targets[p].et_hi;
-        int lo = P.ct_lo, hi = P.ct_hi;
-        if (P.ct_hi <= P.ct_lo) { lo = nC; hi = 0; }
-        for (int ne = P.et_lo; ne < P.et_hi; ++ne) {
-            const int e = c->eperm[ne];
-            for (int s = 0; s < 2; ++s) {
-                const int ci = c->cinv[m->cells_on_edge[2 * e + s]];
-                lo = std::min(lo, ci);
-                hi = std::max(hi, ci + 1);
-            }
-        }
-        if (hi <= lo) { lo = hi = 0; }
-        P.c_lo = lo;
-        P.c_hi = hi;
-        int vlo = c->nV, vhi = 0;
-        std::vector<char> useu(nE, 0), useh(nC, 0), useq(c->nV, 0);
-        long slots = 0;
-        for (int ni = lo; ni < hi; ++ni) {
-            const int i = c->cperm[ni];
-            useh[ni] = 1;
-            for (int j = 0; j < m->n_edges_on_cell[i]; ++j) {
-                const int v = c->vinv[m->vertices_on_cell[(size_t)i * m->max_edges + j]];
-                vlo = std::min(vlo, v);
-                vhi = std::max(vhi, v + 1);
-                useq[v] = 1;
-                useu[c->einv[m->edges_on_cell[(size_t)i * m->max_edges + j]]] = 1;
-                useh[c->cinv[m->cells_on_cell[(size_t)i * m->max_edges + j]]] = 1;
-                ++slots;
-            }
-        }
-        if (vhi <= vlo) { vlo = vhi = 0; }
-        P.v_lo = vlo;
-        P.v_hi = vhi;
-        P.c_uniq_h = std::count(useh.begin(), useh.end(), 1);
-        P.c_uniq_u = std::count(useu.begin(), useu.end(), 1);
-        P.c_uniq_q = std::count(useq.begin(), useq.end(), 1);
-        P.c_slots = slots;
-        std::vector<char> vu(nE, 0), vh(nC, 0);
-        for (int nv = vlo; nv < vhi; ++nv) {
-            const int v = c->vperm[nv];
-            for (int k = 0; k < 3; ++k) {
-                vu[c->einv[m->edges_on_vertex[3 * v + k]]] = 1;
-                vh[c->cinv[m->cells_on_vertex[3 * v + k]]] = 1;
-            }
-        }
-        P.v_uniq_u = std::count(vu.begin(), vu.end(), 1);
-        P.v_uniq_h = std::count(vh.begin(), vh.end(), 1);
-    }
+    for (int p = 0; p < P_N; ++p)
+        c->plan[p] = plan_cover(c, m, targets[p].ct_lo, targets[p].ct_hi, targets[p].et_lo,
+                                targets[p].et_hi);
+    // interface cells and edges only (the surrogate's interface accumulation)
+    c->iface_plan = plan_cover(c, m, cb[3], cb[5], eb[2], eb[4]);
 }
 
 // Enqueue n steps of `scheme`: replayed from a hipGraph captured once per
@@ -745,7 +761,10 @@ lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1,
     c->nC = nC;
     c->nE = nE;
     c->nV = nV;
-    c->maxE = m->max_edges;
+    // lanes per cell follow the largest cell present, not the declared
+    // capacity max_edges (the stride of the caller's arrays)
+    c->maxE = 0;
+    for (int i = 0; i < nC; ++i) c->maxE = std::max(c->maxE, m->n_edges_on_cell[i]);
     c->g = gravity;
     // cell order: class, then Morton key of the position (or input index)
     std::vector<uint64_t> key(nC, 0);

@@ -51,6 +51,7 @@ struct lts_ctx {
     int cb[8] = {0};  // cell class starts: Fint F2 F1 I1 I2 C1 Crest end
     int eb[6] = {0};  // edge class starts: Fint Fbar I1 I2 C end
     lts::PassPlan plan[lts::P_N];
+    lts::PassPlan iface_plan;  // targets I1 u I2 (cells and edges) only
 
     // device memory (typed by prec); all owned
     std::vector<void*> allocs;
@@ -139,11 +140,12 @@ double kernel_bytes(const PassPlan& P, int kclass, const Seg<T>& s0, const Seg<T
     if (kclass == KC_VERTEX)
         return (P.v_hi - P.v_lo) * (3 * 4 * 2 + 7 * ts) +
                L * ((P.v_hi - P.v_lo) * ts + (P.v_uniq_u + P.v_uniq_h) * ts);
-    // per cell: n_i, beta_i and A_i, plus S_n in the single-layer kernel (the
-    // layered one sums the kite fractions itself); per slot: three indices
-    // and four coefficients
+    // per cell: the slot record {first entry, n_i} (8 bytes), beta_i and
+    // 1/A_i, plus S_n in the single-layer kernel (the layered one sums the
+    // kite fractions itself); per real slot: three indices and four
+    // coefficients (the tables hold no padding)
     if (kclass == KC_CELL)
-        return (P.c_hi - P.c_lo) * (4 + (L > 1 ? 2 : 3) * ts) + P.c_slots * (3 * 4 + 4 * ts) +
+        return (P.c_hi - P.c_lo) * (8 + (L > 1 ? 2 : 3) * ts) + P.c_slots * (3 * 4 + 4 * ts) +
                L * (P.c_slots * ts + (P.c_uniq_h + P.c_uniq_u + P.c_uniq_q) * ts +
                     seg_bytes(s0) + seg_bytes(s1));
     return L * ((P.et_hi - P.et_lo) * 2.0 * ts + seg_bytes(s0) + seg_bytes(s1)) +

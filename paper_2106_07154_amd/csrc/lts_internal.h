@@ -17,22 +17,26 @@ constexpr bool perturbation_form() {
 }
 
 // Device mesh, permuted so that every LTS region is a contiguous range.
-// Per-cell slot tables are cell-major with G = padded_slots(maxE) slots per
-// cell ([cell][G]): the cell kernel gives each slot its own lane, so a
-// wavefront reads 64 consecutive table entries.
+// Per-cell slot tables are compact: the n_i slots of cell i (counter-
+// clockwise) are entries cso[i].x .. cso[i].x + n_i - 1, cells one after
+// another in device order, no padding.  The cell kernel gives each slot its
+// own lane (G = padded_slots(maxE) lanes per cell); lanes past n_i re-read
+// the cell's last entry (a cache line already fetched) and zero its
+// coefficients in registers.  A wavefront's table reads are one contiguous
+// run of about 6 entries per cell.
 template <typename T>
 struct DevMesh {
-    int nC, nE, nV, maxE;
-    const int32_t* nEoC;   // [nC]
-    const int32_t* eoc;    // [nC][G] edge of slot j (ccw)
-    const int32_t* coc;    // [nC][G] cell across edge j
-    const int32_t* voc;    // [nC][G] vertex between edge j and j+1
-    const T* nl;           // [nC][G] n_{e,i} l_e
-    const T* nd;           // [nC][G] n_{e,i} / d_e
-    const T* kc;           // [nC][G] l_e d_e / (4 A_i)
-    const T* kf;           // [nC][G] A_{i,v_j} / A_i (kite fraction of vertex slot j)
-    const T* sb;           // [nC][G] S_j: kite fractions of the slots before j summed
-                           //         (padding slots: S_n)
+    int nC, nE, nV, maxE;  // maxE: largest n_i of the mesh
+    const int32_t* nEoC;   // [nC] n_i
+    const int2* cso;       // [nC] {first slot-table entry of cell i, n_i}
+    const int32_t* eoc;    // [slots] edge of slot j (ccw)
+    const int32_t* coc;    // [slots] cell across edge j
+    const int32_t* voc;    // [slots] vertex between edge j and j+1
+    const T* nl;           // [slots] n_{e,i} l_e
+    const T* nd;           // [slots] n_{e,i} / d_e
+    const T* kc;           // [slots] l_e d_e / (4 A_i)
+    const T* kf;           // [slots] A_{i,v_j} / A_i (kite fraction of vertex slot j)
+    const T* sb;           // [slots] S_j: kite fractions of the slots before j summed
     const T* sn;           // [nC] S_n: all kite fractions of the cell summed
     const T* area;         // [nC] A_i
     const T* rarea;        // [nC] 1 / A_i
@@ -118,7 +122,6 @@ hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, i
                         int grid, int G, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 
-// Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch error.
 // Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch
 // error.  With non-null ev0/ev1 the launch goes through hipExtLaunchKernelGGL,
 // which stamps the kernel's own start and end into the two events (timing mode;
@@ -136,7 +139,7 @@ template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0,
                        const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-// Slots per cell in the device tables (and lanes per cell in the cell kernel).
+// Lanes per cell in the cell kernel for a mesh whose largest cell has maxE edges.
 __host__ __device__ inline int padded_slots(int maxE) { return maxE <= 8 ? 8 : 16; }
 // Diagnostics partials per block (mass, energy, h_min, h_max, |u|max, nonfinite)
 // then a single-block deterministic reduction into out[8] (doubles).

@@ -170,8 +170,9 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevMesh<T> m, const T* __rest
 
 // Cell kernel: one lane per edge slot, G lanes per cell (G = 8 or 16), so a
 // wave64 covers 64/G cells and every slot's gathers are issued by its own
-// lane.  Slot tables are cell-major ([cell][G]); slots n..G-1 are padding with
-// valid indices (copies of slot n-1) and zero coefficients.
+// lane.  Slot tables are compact (the cell's n slots from cso[i].x); lanes
+// n..G-1 are padding: they re-read slot n-1 (valid indices, so lane G-1
+// holds the PV of the vertex before slot 0) with zero coefficients.
 //
 // The PV part of Z_i(b) is rewritten with prefix sums: with S_a the kite
 // fractions summed counter-clockwise before slot a and S_n their total (both
@@ -262,17 +263,19 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     CellLane<T> c;
     const T* __restrict__ href = m.href;
     const bool hr = present<HR>(href);
-    c.o = (size_t)i * G + lane;
+    const int2 so = m.cso[i];
+    c.n = so.y;
+    // lanes past the cell's last slot re-read that slot, coefficients zeroed
+    c.o = (size_t)so.x + min(lane, so.y - 1);
     c.i = i;
     c.lane = lane;
     c.live = live;
     c.e = m.eoc[c.o];
     const int nb = m.coc[c.o];
-    c.nl = m.nl[c.o];
-    c.kc = m.kc[c.o];
+    c.nl = lane < so.y ? m.nl[c.o] : T(0);
+    c.kc = lane < so.y ? m.kc[c.o] : T(0);
     c.sb = m.sb[c.o];
     c.nd = m.nd[c.o];
-    c.n = m.nEoC[i];
     c.sn = m.sn[i];
     c.hc = h[i];
     c.hi = hr ? href[i] + c.hc : c.hc;
@@ -466,10 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_diag_part(DevMesh<T> m, const T* __r
         if (i < m.nC) {
             const double hi = m.href ? (double)m.href[i] + (double)h[il] : (double)h[il];
             double K = 0.0;
-            const int n = m.nEoC[i];
-            const int G = padded_slots(m.maxE);
-            for (int a = 0; a < n; ++a) {
-                const size_t o = (size_t)i * G + a;
+            const int2 so = m.cso[i];
+            for (int a = 0; a < so.y; ++a) {
+                const size_t o = (size_t)so.x + a;
                 const double ue = (double)u[(size_t)m.eoc[o] * L + l];
                 K += (double)m.kc[o] * ue * ue;
             }
@@ -657,21 +659,23 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     const T* __restrict__ kc = m.kc;
     const T* __restrict__ kf = m.kf;
     const T* __restrict__ href = m.href;
-    const int n = m.nEoC[i];
+    const int2 so = m.cso[i];
+    const int n = so.y;
     const size_t il = (size_t)i * L + l;
     const bool hr = present<HR>(href);
     const T hi = hr ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
-    T qprev = q[(size_t)voc[(size_t)i * G + n - 1] * L + l];
-    // Every slot, padding included: padding slots repeat the last slot's
-    // indices with zero coefficients, so they add exact zeros to the sums
+    T qprev = q[(size_t)voc[(size_t)so.x + n - 1] * L + l];
+    // Every slot up to G, padding included: padding slots re-read the last
+    // slot with its coefficients zeroed, so they add exact zeros to the sums
     // and only their stores are skipped.  Without a branch per slot all the
     // slots' loads can be in flight together.
-    T X1[G], X2[G], qtA[G];
+    T X1[G], X2[G], qtA[G], kfA[G];
     T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        const size_t o = (size_t)i * G + a;
+        const bool real = a < n;
+        const size_t o = (size_t)so.x + min(a, n - 1);
         const int e = eoc[o], nb = coc[o];
         const T ue = u[(size_t)e * L + l];
         const T hn0 = h[(size_t)nb * L + l];
@@ -679,12 +683,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
         const T qa = q[(size_t)voc[o] * L + l];
         const T qt = T(0.5) * (qprev + qa);
         qprev = qa;
-        X1[a] = nl[o] * (T(0.5) * (hi + hn) * ue);
+        X1[a] = real ? nl[o] * (T(0.5) * (hi + hn) * ue) : T(0);
         X2[a] = X1[a] * qt;
         qtA[a] = qt;
-        K += kc[o] * ue * ue;
+        K += real ? kc[o] * ue * ue : T(0);
+        kfA[a] = real ? kf[o] : T(0);
         const T Sb = S;
-        S += kf[o];
+        S += kfA[a];
         t1 += X1[a];
         t2 += X2[a];
         p1 += Sb * X1[a];
@@ -694,9 +699,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     T c1 = 0, c2 = 0, Sr = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        const size_t o = (size_t)i * G + a;
+        const size_t o = (size_t)so.x + min(a, n - 1);
         const T Sb = Sr;
-        Sr += kf[o];
+        Sr += kfA[a];
         c1 += X1[a];
         c2 += X2[a];
         const T P1 = (Sb - T(0.5)) * (t1 - X1[a]) - (p1 - Sb * X1[a]) + S * (t1 - c1);

@@ -512,13 +512,14 @@ __global__ void k_build_graph(DevMesh<T> m, int N, int nFe, int32_t* __restrict_
                               int32_t* __restrict__ ec0, int32_t* __restrict__ ec1) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    const int G = padded_slots(m.maxE);
-    const int n = m.nEoC[i];
+    const int G = padded_slots(m.maxE);  // adjacency width
+    const int2 so = m.cso[i];
+    const int n = so.y;
     int deg = 0;
     for (int s = 0; s < G; ++s) {
         int nb = -1, code = -1;
         if (s < n) {
-            const size_t o = (size_t)i * G + s;
+            const size_t o = (size_t)so.x + s;
             const int j = m.coc[o];
             if (j >= 0 && j < N) {
                 nb = j;
@@ -542,12 +543,12 @@ __global__ void k_features(DevMesh<T> m, const T* __restrict__ h, const T* __res
                            int cb1, int cb3, int cb4, float* __restrict__ raw) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    const int G = padded_slots(m.maxE);
-    const int n = m.nEoC[i];
+    const int2 so = m.cso[i];
+    const int n = so.y;
     const int nV = m.nV;
     T div = 0, K = 0, vort = 0;
     for (int s = 0; s < n; ++s) {
-        const size_t o = (size_t)i * G + s;
+        const size_t o = (size_t)so.x + s;
         const T ue = u[m.eoc[o]];
         div += m.nl[o] * ue;
         K += m.kc[o] * ue * ue;

@@ -150,3 +150,49 @@ def test_wide_cell_ensemble(wide, irregular, prec):
     rh, ru = o.lts(h, u, dt, 4, o.regions(masks["fine11"], 2, 2), n=3)
     assert rel_l2(gh, rh, m.areaCell) < (1e-12 if prec == "fp64" else 1e-5)
     ens.close()
+
+
+def _restride(m, cap):
+    """The same mesh with its per-cell arrays declared at capacity `cap`
+    (MPAS meshes declare maxEdges = 10 or more whatever the cells hold);
+    unused entries are -1."""
+    w = m.copy()
+    w.maxEdges = cap
+    for name in ("edgesOnCell", "cellsOnCell", "verticesOnCell"):
+        a = getattr(m, name)
+        b = np.full((m.nCells, cap), -1, dtype=a.dtype)
+        b[:, :a.shape[1]] = a
+        for i in range(m.nCells):
+            b[i, m.nEdgesOnCell[i]:] = -1
+        setattr(w, name, b)
+    return w
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_declared_capacity_is_not_the_lane_count(hex16, prec):
+    """A hexagonal mesh declared with max_edges = 16 runs the same kernels as
+    the same mesh declared with 6: the lane count follows the largest cell
+    present.  Results are bitwise those of the compact declaration and match
+    the oracle (FP64 1e-12 h, 1e-11 u; FP32 1e-5)."""
+    import torch
+    from paper_2106_07154_amd.inputs import igw_parameters, igw_state, strip_fine_mask
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("declared capacity 16", prec)
+    m = hex16
+    w = _restride(m, 16)
+    fm = strip_fine_mask(m, 6, 9, 1.0e4)
+    h0, u0 = igw_state(m, igw_parameters(m), 0.0)
+    out = []
+    for mesh in (m, w):
+        c = lts.LTSContext(0, prec)
+        c.upload_mesh(mesh, fm, 2, 2)
+        c.init_state(h0, u0)
+        c.step(30.0, 4, 6)
+        out.append(c.get_state())
+        c.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    o = Oracle(m)
+    rh, ru = o.lts(h0, u0, 30.0, 4, o.regions(fm, 2, 2), n=6)
+    tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
+    assert rel_l2(out[1][0], rh) < tol_h and rel_l2(out[1][1], ru) < tol_u

@@ -103,21 +103,30 @@ lts_status lts_sur_features(lts_sur *s, float *raw);
    normalised units, for the current context state. */
 lts_status lts_sur_predict(lts_sur *s, float *out_h, float *out_u);
 
-/* n_steps gated coarse steps of size dt: the network advances F; I u C take
-   one SSPRK3 step of size dt (Algorithm 2.1) on the Step-2 pass set, reading
-   F at t, t + dt and t + dt/2 as x_n, the prediction and their mean; then
+/* n_steps gated coarse steps of size dt with fine ratio M: the network
+   advances F; I1, I2 and C follow Algorithm 2.2 with the fine substeps
+   replaced by the prediction: Steps 1 and 2 (the coarse stages on
+   underlined F, I and C), the interface accumulation of Step 3 over all 3M
+   fine stages (F read linearly in time between x_n and the prediction at
+   the SSPRK3 stage times t_k, t_k + dt/M, t_k + dt/(2M); interface 1
+   predicted from the coarse stages as in Steps 3.x.1; I2 and C at the coarse
+   stage), Step 4 on C and Step 5 on I1 u I2.  F then takes the prediction,
+   its thickness shifted uniformly by the step's total mass change divided
+   by the area of F, so an accepted step conserves mass to rounding.  Then
      r = max over (h on fine cells, u on fine edges) of
-         || (x_pred - x_n)/dt - (R(x_n) + R(x_pred))/2 ||
-         / ((|| R(x_n) || + || R(x_pred) ||) / 2)
-   (the trapezoid-rule defect of the step; L2 norms over the fine cells or
-   fine edges).  A step with r < tau is kept, any other (r NaN included) is
+         || (x_new - x_n)/dt - (R(x_n) + R(x_new))/2 ||
+         / ((|| R(x_n) || + || R(x_new) ||) / 2)
+   (the trapezoid-rule defect of the step on F; L2 norms over the fine cells
+   or fine edges).  A step with r < tau is kept, any other (r NaN included) is
    recomputed from x_n by the plain LTS3 step (dt, M).  With max_backoff > 0
    a rejection also skips the surrogate for the next b steps (plain LTS3),
    b doubling with every further rejection up to max_backoff and resetting on
    an acceptance; the back-off state persists across calls.  max_backoff = 0
    tries the surrogate on every step.  n_accepted and residuals[n_steps]
    (-1 for a skipped step; either may be NULL) report the outcome.
-   Synchronises once per attempted step. */
+   Synchronises once per attempted step.  The first call with a new (dt, M)
+   allocates the 3M-layer stage buffers of the interface accumulation and
+   captures the step's graph. */
 lts_status lts_sur_step(lts_sur *s, double dt, int M, int n_steps, double tau, int max_backoff,
                         int *n_accepted, double *residuals);
 

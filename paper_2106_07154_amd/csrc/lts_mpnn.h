@@ -102,10 +102,35 @@ template <typename T>
 void apply_increments(const T* h, const T* u, const T* R0h, const T* R0u, double dt,
                       const float* out_h, const float* out_u, const float* scale, int nF, int nFe,
                       T* xh, T* xu, hipStream_t s);
-// On i < nF (cells) and e < nFe (edges): mid = (a + b) / 2, then a = b.
+// Sources of one field for the interface accumulation's stage states: x0, x1,
+// x2 the coarse stages X0, X1, X2 (full arrays, device order), pred the
+// surrogate's state at t + dt on the fine elements, i0, i1, i2 the
+// interface-1 copies of X0, X1, X2.
 template <typename T>
-void midpoint_and_commit(T* ah, T* au, const T* bh, const T* bu, T* mh, T* mu, int nF, int nFe,
-                         hipStream_t s);
+struct IfaceSrc {
+    const T *x0, *x1, *x2, *pred, *i0, *i1, *i2;
+};
+// Stage states [element][L] (L = 3M, layer 3k + s) on the listed elements
+// (cells cidx with class ccls, then edges): class 0 fine, linear in time
+// between x0 and pred (coef[4 l] = tau); class 1 interface 1, the prediction
+// coef[4 l + 1..3] . (i0, i1, i2); class 2 interface 2 or coarse, x_s.
+template <typename T>
+void iface_fill(const int32_t* cidx, const int8_t* ccls, int ncl, const int32_t* eidx,
+                const int8_t* ecls, int nel, int L, const double* coef, const IfaceSrc<T>& h,
+                const IfaceSrc<T>& u, int cb3, int eb2, T* hS, T* uS, hipStream_t s);
+// x[lo + j] = x0[lo + j] + delta sum_k (acc[j][3k]/6 + acc[j][3k+1]/6 +
+// 2 acc[j][3k+2]/3) on the nIc interface cells (lo = cb3) and nIe interface
+// edges (lo = eb2), FP64 sums.
+template <typename T>
+void iface_combine(const T* acch, const T* accu, int nIc, int nIe, int L, double delta, int cb3,
+                   int eb2, const T* x0h, const T* x0u, T* xh, T* xu, hipStream_t s);
+// Remove the mass change sum_i A_i (h1_i - h0_i) from the fine cells
+// 0..nF-1 of h1 as a uniform thickness shift (change * inv_area_f);
+// part[mass_fix_parts(nC)], shift[1] device scratch.
+int mass_fix_parts(int nC);
+template <typename T>
+void mass_fix(const T* area, const T* h0, T* h1, int nC, int nF, double inv_area_f, double* part,
+              double* shift, hipStream_t s);
 // Trapezoid residual sums on the fine region, FP64:
 //   out[0] = sum_i ((x1-x0)/dt - (R0+R1)/2)^2 over cells, out[1] = sum R0^2,
 //   out[2] = sum R1^2, out[3..5] the same over edges.

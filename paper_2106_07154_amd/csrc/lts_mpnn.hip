@@ -600,21 +600,98 @@ __global__ void k_apply(const T* __restrict__ h, const T* __restrict__ u,
     }
 }
 
+// Stage states of the interface accumulation, L = 3M layers [element][L]
+// (layer l = 3k + s: stage s of fine substep k), on the elements the
+// interface pass reads: fine (cls 0) = x_n + tau_l (x_pred - x_n); interface 1
+// (cls 1) = c0 X0 + c1 X1 + c2 X2 from its copies of the coarse stages;
+// interface 2 and coarse (cls 2) = the coarse stage X_s.  Coefficients are
+// FP64 (coef[l] = {tau, c0, c1, c2}); entries past ncl are edges.
 template <typename T>
-__global__ void k_midpoint(T* __restrict__ ah, T* __restrict__ au, const T* __restrict__ bh,
-                           const T* __restrict__ bu, T* __restrict__ mh, T* __restrict__ mu,
-                           int nF, int nFe) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < nF) {
-        const T a = ah[t], b = bh[t];
-        mh[t] = T(0.5) * (a + b);
-        ah[t] = b;
-    } else if (t < nF + nFe) {
-        const int e = t - nF;
-        const T a = au[e], b = bu[e];
-        mu[e] = T(0.5) * (a + b);
-        au[e] = b;
+__global__ void k_iface_fill(const int32_t* __restrict__ cidx, const int8_t* __restrict__ ccls,
+                             int ncl, const int32_t* __restrict__ eidx,
+                             const int8_t* __restrict__ ecls, int nel, int L,
+                             const double* __restrict__ coef, IfaceSrc<T> h, IfaceSrc<T> u,
+                             int cb3, int eb2, T* __restrict__ hS, T* __restrict__ uS) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const long ent = t / L;
+    const int l = (int)(t % L);
+    if (ent >= (long)ncl + nel) return;
+    const bool cell = ent < ncl;
+    const IfaceSrc<T>& x = cell ? h : u;
+    const int j = cell ? cidx[ent] : eidx[ent - ncl];
+    const int cls = cell ? ccls[ent] : ecls[ent - ncl];
+    const int lo = cell ? cb3 : eb2;
+    const double* c = coef + 4 * l;
+    double v;
+    if (cls == 0) {
+        const double a = (double)x.x0[j];
+        v = a + c[0] * ((double)x.pred[j] - a);
+    } else if (cls == 1) {
+        const int k = j - lo;
+        v = c[1] * (double)x.i0[k] + c[2] * (double)x.i1[k] + c[3] * (double)x.i2[k];
+    } else {
+        const int st = l % 3;
+        v = (double)(st == 0 ? x.x0[j] : st == 1 ? x.x1[j] : x.x2[j]);
     }
+    (cell ? hS : uS)[(size_t)j * L + l] = (T)v;
+}
+
+// Interface correction from the stage tendencies: x[lo + j] = x_n[lo + j]
+// + delta sum_k (G_k0 / 6 + G_k1 / 6 + 2 G_k2 / 3), sums in FP64.
+template <typename T>
+__global__ void k_iface_combine(const T* __restrict__ acch, const T* __restrict__ accu, int nIc,
+                                int nIe, int L, double delta, int cb3, int eb2,
+                                const T* __restrict__ x0h, const T* __restrict__ x0u,
+                                T* __restrict__ xh, T* __restrict__ xu) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nIc + nIe) return;
+    const bool cell = t < nIc;
+    const int k = cell ? t : t - nIc;
+    const T* a = (cell ? acch : accu) + (size_t)k * L;
+    double sum = 0.0;
+    for (int l = 0; l + 2 < L; l += 3)
+        sum += (double)a[l] / 6.0 + (double)a[l + 1] / 6.0 + 2.0 * (double)a[l + 2] / 3.0;
+    const int j = (cell ? cb3 : eb2) + k;
+    if (cell) xh[j] = (T)((double)x0h[j] + delta * sum);
+    else xu[j] = (T)((double)x0u[j] + delta * sum);
+}
+
+// Mass change sum_i A_i (h1_i - h0_i) over all cells: FP64 block partials in
+// a fixed tree order, then one block sums them and stores the thickness
+// shift that removes it from the fine cells (the change divided by their
+// total area, inv_area_f = 1 / sum over fine cells of A_i).
+template <typename T>
+__global__ void k_mass_part(const T* __restrict__ area, const T* __restrict__ h0,
+                            const T* __restrict__ h1, int nC, double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    __shared__ double sm[256];
+    sm[threadIdx.x] = i < nC ? (double)area[i] * ((double)h1[i] - (double)h0[i]) : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_mass_final(const double* __restrict__ part, int nparts, double inv_area_f,
+                             double* __restrict__ shift) {
+    __shared__ double sm[256];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256) a += part[b];
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) shift[0] = sm[0] * inv_area_f;
+}
+
+template <typename T>
+__global__ void k_mass_apply(T* __restrict__ h, int nF, const double* __restrict__ shift) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nF) h[i] = (T)((double)h[i] - shift[0]);
 }
 
 template <typename T>
@@ -810,11 +887,36 @@ void apply_increments(const T* h, const T* u, const T* R0h, const T* R0u, double
 }
 
 template <typename T>
-void midpoint_and_commit(T* ah, T* au, const T* bh, const T* bu, T* mh, T* mu, int nF, int nFe,
-                         hipStream_t s) {
-    if (nF + nFe > 0)
-        hipLaunchKernelGGL((k_midpoint<T>), dim3(nblk((long)nF + nFe, 256)), dim3(256), 0, s, ah,
-                           au, bh, bu, mh, mu, nF, nFe);
+void iface_fill(const int32_t* cidx, const int8_t* ccls, int ncl, const int32_t* eidx,
+                const int8_t* ecls, int nel, int L, const double* coef, const IfaceSrc<T>& h,
+                const IfaceSrc<T>& u, int cb3, int eb2, T* hS, T* uS, hipStream_t s) {
+    const long n = ((long)ncl + nel) * L;
+    if (n > 0)
+        hipLaunchKernelGGL((k_iface_fill<T>), dim3(nblk(n, 256)), dim3(256), 0, s, cidx, ccls, ncl,
+                           eidx, ecls, nel, L, coef, h, u, cb3, eb2, hS, uS);
+}
+
+template <typename T>
+void iface_combine(const T* acch, const T* accu, int nIc, int nIe, int L, double delta, int cb3,
+                   int eb2, const T* x0h, const T* x0u, T* xh, T* xu, hipStream_t s) {
+    if (nIc + nIe > 0)
+        hipLaunchKernelGGL((k_iface_combine<T>), dim3(nblk((long)nIc + nIe, 256)), dim3(256), 0, s,
+                           acch, accu, nIc, nIe, L, delta, cb3, eb2, x0h, x0u, xh, xu);
+}
+
+int mass_fix_parts(int nC) { return (int)nblk(nC, 256); }
+
+template <typename T>
+void mass_fix(const T* area, const T* h0, T* h1, int nC, int nF, double inv_area_f, double* part,
+              double* shift, hipStream_t s) {
+    const int np = mass_fix_parts(nC);
+    if (np == 0 || nF == 0) return;
+    hipLaunchKernelGGL((k_mass_part<T>), dim3(np), dim3(256), 0, s, area, h0, (const T*)h1, nC,
+                       part);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, (const double*)part, np, inv_area_f,
+                       shift);
+    hipLaunchKernelGGL((k_mass_apply<T>), dim3(nblk(nF, 256)), dim3(256), 0, s, h1, nF,
+                       (const double*)shift);
 }
 
 template <typename T>
@@ -838,8 +940,13 @@ void gate_sums(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h,
     template void apply_increments<T>(const T*, const T*, const T*, const T*, double,            \
                                       const float*, const float*, const float*, int, int, T*,    \
                                       T*, hipStream_t);                                          \
-    template void midpoint_and_commit<T>(T*, T*, const T*, const T*, T*, T*, int, int,           \
-                                         hipStream_t);                                           \
+    template void iface_fill<T>(const int32_t*, const int8_t*, int, const int32_t*,             \
+                                const int8_t*, int, int, const double*, const IfaceSrc<T>&,      \
+                                const IfaceSrc<T>&, int, int, T*, T*, hipStream_t);              \
+    template void iface_combine<T>(const T*, const T*, int, int, int, double, int, int,          \
+                                   const T*, const T*, T*, T*, hipStream_t);                     \
+    template void mass_fix<T>(const T*, const T*, T*, int, int, double, double*, double*,        \
+                              hipStream_t);                                                      \
     template void gate_sums<T>(const T*, const T*, const T*, const T*, const T*, const T*,       \
                                const T*, const T*, int, int, double, double*, double*,           \
                                hipStream_t);

@@ -3,6 +3,7 @@
 // lts_surrogate.h).  The network kernels live in lts_mpnn.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -63,7 +64,20 @@ struct lts_sur {
     int* flag = nullptr;
     // state-typed buffers (context precision)
     void *Sh = nullptr, *Su = nullptr, *R0h = nullptr, *R0u = nullptr, *R1h = nullptr,
-         *R1u = nullptr;
+         *R1u = nullptr, *Ph = nullptr, *Pu = nullptr;
+    // interface accumulation: the elements its pass reads (device numbering)
+    // with their class (0 fine, 1 interface 1, 2 interface 2 or coarse), and
+    // the stage buffers of L = 3M layers (allocated for the M in use)
+    int32_t *icidx = nullptr, *ieidx = nullptr;
+    int8_t *iccls = nullptr, *iecls = nullptr;
+    int nicl = 0, niel = 0;
+    int L = 0;
+    void *hS = nullptr, *uS = nullptr, *qS = nullptr, *zsS = nullptr, *accH = nullptr,
+         *accU = nullptr;
+    double* icoef = nullptr;
+    // mass fix: 1 / (area of the fine cells), scratch
+    double inv_area_f = 0.0;
+    double *mpart = nullptr, *mshift = nullptr;
 
     float norm_host[16] = {0};
     bool has_norm = false;
@@ -73,6 +87,7 @@ struct lts_sur {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     double g_dt = 0.0;
+    int g_M = 0;
 };
 
 namespace {
@@ -178,6 +193,104 @@ void backward(lts_sur* s) {
     nn::colsum(s->dZ, N, RPB, s->part, s->g + off_b(0), s->s);
 }
 
+// The cells and edges the interface-only pass reads (its cell range, their
+// neighbours and edges, and the cells and edges of its vertex range), with
+// the class that decides their stage values.
+template <typename T>
+lts_status interface_read_set(lts_sur* s) {
+    lts_ctx* c = s->c;
+    const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    const PassPlan& P = c->iface_plan;
+    const int nC = c->nC, nE = c->nE, nV = c->nV;
+    std::vector<int32_t> cso(2 * (size_t)nC);
+    SCHK(s, hipMemcpy(cso.data(), dm.cso, cso.size() * 4, hipMemcpyDeviceToHost));
+    const size_t nslots = nC ? (size_t)cso[2 * (size_t)(nC - 1)] + cso[2 * (size_t)nC - 1] : 0;
+    std::vector<int32_t> eoc(nslots), coc(nslots), eov(3 * (size_t)nV), cov(3 * (size_t)nV);
+    SCHK(s, hipMemcpy(eoc.data(), dm.eoc, nslots * 4, hipMemcpyDeviceToHost));
+    SCHK(s, hipMemcpy(coc.data(), dm.coc, nslots * 4, hipMemcpyDeviceToHost));
+    SCHK(s, hipMemcpy(eov.data(), dm.eov, eov.size() * 4, hipMemcpyDeviceToHost));
+    SCHK(s, hipMemcpy(cov.data(), dm.cov, cov.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<char> rc(nC, 0), re(nE, 0);
+    for (int i = P.c_lo; i < P.c_hi; ++i) {
+        rc[i] = 1;
+        for (int a = 0; a < cso[2 * (size_t)i + 1]; ++a) {
+            const size_t o = (size_t)cso[2 * (size_t)i] + a;
+            rc[coc[o]] = 1;
+            re[eoc[o]] = 1;
+        }
+    }
+    for (int v = P.v_lo; v < P.v_hi; ++v)
+        for (int k = 0; k < 3; ++k) {
+            rc[cov[(size_t)k * nV + v]] = 1;
+            re[eov[(size_t)k * nV + v]] = 1;
+        }
+    std::vector<int32_t> ci, ei;
+    std::vector<int8_t> cc, ec;
+    for (int i = 0; i < nC; ++i)
+        if (rc[i]) {
+            ci.push_back(i);
+            cc.push_back((int8_t)(i < c->cb[3] ? 0 : i < c->cb[4] ? 1 : 2));
+        }
+    for (int e = 0; e < nE; ++e)
+        if (re[e]) {
+            ei.push_back(e);
+            ec.push_back((int8_t)(e < c->eb[2] ? 0 : e < c->eb[3] ? 1 : 2));
+        }
+    s->nicl = (int)ci.size();
+    s->niel = (int)ei.size();
+    lts_status st;
+    if ((st = salloc(s, &s->icidx, ci.size() * 4)) || (st = salloc(s, &s->iccls, cc.size())) ||
+        (st = salloc(s, &s->ieidx, ei.size() * 4)) || (st = salloc(s, &s->iecls, ec.size())))
+        return st;
+    SCHK(s, hipMemcpy(s->icidx, ci.data(), ci.size() * 4, hipMemcpyHostToDevice));
+    SCHK(s, hipMemcpy(s->iccls, cc.data(), cc.size(), hipMemcpyHostToDevice));
+    SCHK(s, hipMemcpy(s->ieidx, ei.data(), ei.size() * 4, hipMemcpyHostToDevice));
+    SCHK(s, hipMemcpy(s->iecls, ec.data(), ec.size(), hipMemcpyHostToDevice));
+    return LTS_OK;
+}
+
+// Stage buffers for L = 3M layers and the per-layer coefficients: tau of the
+// fine stage time (SSPRK3 stages at t_k, t_k + dt/M, t_k + dt/(2M)) and the
+// interface-1 prediction of Algorithm 2.2 (Steps 3.1.1, 3.2.1, 3.3.1).
+template <typename T>
+lts_status stage_buffers(lts_sur* s, int M) {
+    lts_ctx* c = s->c;
+    const int L = 3 * M;
+    if (s->L == L) return LTS_OK;
+    SCHK(s, hipStreamSynchronize(s->s));
+    for (void** b : {&s->hS, &s->uS, &s->qS, &s->zsS, &s->accH, &s->accU,
+                     reinterpret_cast<void**>(&s->icoef)}) {
+        if (*b) {
+            s->allocs.erase(std::find(s->allocs.begin(), s->allocs.end(), *b));
+            (void)hipFree(*b);
+            *b = nullptr;
+        }
+    }
+    s->L = 0;
+    const size_t ts = sizeof(T) * (size_t)L;
+    const int nIc = c->cb[5] - c->cb[3], nIe = c->eb[4] - c->eb[2];
+    lts_status st;
+    if ((st = salloc(s, &s->hS, c->nC * ts)) || (st = salloc(s, &s->uS, c->nE * ts)) ||
+        (st = salloc(s, &s->qS, c->nV * ts)) || (st = salloc(s, &s->zsS, 2 * c->nE * ts)) ||
+        (st = salloc(s, &s->accH, nIc * ts)) || (st = salloc(s, &s->accU, nIe * ts)) ||
+        (st = salloc(s, &s->icoef, (size_t)L * 4 * 8)))
+        return st;
+    // elements the pass reads but nothing fills stay at zero
+    SCHK(s, hipMemset(s->hS, 0, c->nC * ts));
+    SCHK(s, hipMemset(s->uS, 0, c->nE * ts));
+    std::vector<double> cf(4 * (size_t)L);
+    const double frac[3] = {0.0, 1.0, 0.5};
+    for (int k = 0; k < M; ++k)
+        for (int st3 = 0; st3 < 3; ++st3) {
+            double* q = cf.data() + 4 * (3 * k + st3);
+            q[0] = (k + frac[st3]) / M;
+            Run<double>::predict_coeffs(st3, k, M, q + 1, 3);
+        }
+    SCHK(s, hipMemcpy(s->icoef, cf.data(), cf.size() * 8, hipMemcpyHostToDevice));
+    s->L = L;
+    return LTS_OK;
+}
+
 template <typename T>
 lts_status setup_typed(lts_sur* s) {
     lts_ctx* c = s->c;
@@ -185,9 +298,16 @@ lts_status setup_typed(lts_sur* s) {
     const size_t ts = sizeof(T);
     if ((st = salloc(s, &s->Sh, c->nC * ts)) || (st = salloc(s, &s->Su, c->nE * ts)) ||
         (st = salloc(s, &s->R0h, s->nF * ts)) || (st = salloc(s, &s->R0u, s->nFe * ts)) ||
-        (st = salloc(s, &s->R1h, s->nF * ts)) || (st = salloc(s, &s->R1u, s->nFe * ts)))
+        (st = salloc(s, &s->R1h, s->nF * ts)) || (st = salloc(s, &s->R1u, s->nFe * ts)) ||
+        (st = salloc(s, &s->Ph, s->nF * ts)) || (st = salloc(s, &s->Pu, s->nFe * ts)) ||
+        (st = salloc(s, &s->mpart, (size_t)nn::mass_fix_parts(c->nC) * 8)) ||
+        (st = salloc(s, &s->mshift, 8)))
         return st;
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
+    if ((st = interface_read_set<T>(s))) return st;
+    double af = 0.0;
+    for (int i = 0; i < s->nF; ++i) af += (double)(T)c->area_perm[i];
+    s->inv_area_f = 1.0 / af;
     SCHK(s, hipMemsetAsync(s->ec0, 0xFF, s->nFe * 4, s->s));
     SCHK(s, hipMemsetAsync(s->ec1, 0xFF, s->nFe * 4, s->s));
     nn::build_graph<T>(dm, s->N, s->nFe, s->adj, s->inv_deg, s->node_edges, s->ec0, s->ec1, s->s);
@@ -242,54 +362,96 @@ lts_status record_typed(lts_sur* s, double dt, int M, int n) {
     return LTS_OK;
 }
 
-// The surrogate coarse step up to the gate sums (captured once per dt).
+// The surrogate coarse step up to the gate sums (captured once per dt, M).
+// F: the network's prediction.  I1, I2, C: Algorithm 2.2 with the fine
+// substeps replaced by the surrogate: Steps 1 and 2 (coarse stages on
+// underlined F, I and C), the interface accumulation of Step 3 over all 3M
+// fine stages at once (F read linearly in time between x_n and the
+// prediction, I1 predicted, I2 and C at the coarse stages), Step 4 on C,
+// Step 5 on I.  Then the mass change of the whole step is removed from F as
+// a uniform thickness shift, so mass is conserved to rounding.
 template <typename T>
-lts_status enqueue_sur_step(lts_sur* s, double dt) {
+lts_status enqueue_sur_step(lts_sur* s, double dt, int M) {
     lts_ctx* c = s->c;
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
     Run<T> r{c, dm, s->s, false};
     T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
       *Cu = (T*)c->Cu;
     T *R0h = (T*)s->R0h, *R0u = (T*)s->R0u, *R1h = (T*)s->R1h, *R1u = (T*)s->R1u;
+    T *Ph = (T*)s->Ph, *Pu = (T*)s->Pu, *Sh = (T*)s->Sh, *Su = (T*)s->Su;
     const int* cb = c->cb;
     const int* eb = c->eb;
-    const int nC = c->nC, nE = c->nE;
+    const int nC = c->nC, nE = c->nE, L = s->L;
     const Seg<T> none;
     lts_status st;
-    SCHK(s, hipMemcpyAsync(s->Sh, Ah, nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
-    SCHK(s, hipMemcpyAsync(s->Su, Au, nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
+    SCHK(s, hipMemcpyAsync(Sh, Ah, nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
+    SCHK(s, hipMemcpyAsync(Su, Au, nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     // R(x_n) on F
     if ((st = fine_rhs<T>(s, Ah, Au, R0h, R0u))) return st;
-    // F at t + dt into B: a forward-Euler step plus the network's correction
+    // F at t + dt: a forward-Euler step plus the network's correction
     features_of_state<T>(s, s->raw);
     nn::norm_features(s->raw, s->N, s->norm, s->norm + 5, s->X, s->s);
     forward(s, nullptr, nullptr, nullptr);
     nn::apply_increments<T>(Ah, Au, R0h, R0u, dt, s->out_h, s->out_u, s->norm + 12, s->nF, s->nFe,
-                            Bh, Bu, s->s);
-    // SSPRK3 on I u C with F read at t, t + dt, t + dt/2
-    if ((st = r.pass(P_STEP2, Ah, Au, Run<T>::upd(cb[3], nC, Bh, nullptr, 0, Ah, 1, dt), none,
-                     Run<T>::upd(eb[2], nE, Bu, nullptr, 0, Au, 1, dt), none)))
-        return st;
-    if ((st = r.pass(P_STEP2, Bh, Bu, Run<T>::upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt),
-                     none, Run<T>::upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), none)))
-        return st;
-    nn::midpoint_and_commit<T>(Ah, Au, Bh, Bu, Ch, Cu, s->nF, s->nFe, s->s);
-    if ((st = r.pass(P_STEP2, Ch, Cu,
-                     Run<T>::upd(cb[3], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt), none,
-                     Run<T>::upd(eb[2], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                            Ph, Pu, s->s);
+    // Steps 1 and 2, with the interface-1 copies of X0, X1, X2
+    if ((st = r.pass(P_STEP1, Ah, Au,
+                     Run<T>::mirror(Run<T>::upd(cb[1], nC, Bh, nullptr, 0, Ah, 1, dt), cb[3],
+                                    cb[4], (T*)c->x1h, (T*)c->x0h),
+                     none,
+                     Run<T>::mirror(Run<T>::upd(eb[1], nE, Bu, nullptr, 0, Au, 1, dt), eb[2],
+                                    eb[3], (T*)c->x1u, (T*)c->x0u),
                      none)))
         return st;
-    // R(x_pred) on F (I1 now at t + dt) and the residual sums
+    if ((st = r.pass(P_STEP2, Bh, Bu,
+                     Run<T>::mirror(Run<T>::upd(cb[3], nC, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt),
+                                    cb[3], cb[4], (T*)c->x2h, nullptr),
+                     none,
+                     Run<T>::mirror(Run<T>::upd(eb[2], nE, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt),
+                                    eb[2], eb[3], (T*)c->x2u, nullptr),
+                     none)))
+        return st;
+    // Step 3 on the interface only: the 3M stage states are all known, so
+    // their right-hand sides run as one layered pass (layer 3k + s)
+    const nn::IfaceSrc<T> hsrc{Sh, Bh, Ch, Ph, (T*)c->x0h, (T*)c->x1h, (T*)c->x2h};
+    const nn::IfaceSrc<T> usrc{Su, Bu, Cu, Pu, (T*)c->x0u, (T*)c->x1u, (T*)c->x2u};
+    nn::iface_fill<T>(s->icidx, s->iccls, s->nicl, s->ieidx, s->iecls, s->niel, L, s->icoef, hsrc,
+                      usrc, cb[3], eb[2], (T*)s->hS, (T*)s->uS, s->s);
+    SCHK(s, hipGetLastError());
+    const PassPlan& P = c->iface_plan;
+    SCHK(s, launch_vertex_l<T>(dm, (T*)s->hS, (T*)s->uS, (T*)s->qS, P.v_lo, P.v_hi, L, s->s));
+    SCHK(s, launch_cell_l<T>(dm, (T*)s->hS, (T*)s->uS, (T*)s->qS, (T*)s->zsS, P.c_lo, P.c_hi, L,
+                             (T)c->g, Run<T>::accum(cb[3], cb[5], (T*)s->accH, 1.0, true), none,
+                             c->flag, s->s));
+    SCHK(s, launch_edge_l<T>((T*)s->zsS, nE, P.et_lo, P.et_hi, L,
+                             Run<T>::accum(eb[2], eb[4], (T*)s->accU, 1.0, true), none, Aux<T>(),
+                             c->flag, s->s));
+    // Step 4 on C (reads X2 on I2 and C only)
+    if ((st = r.pass(P_STEP4, Ch, Cu,
+                     Run<T>::upd(cb[5], nC, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                     none,
+                     Run<T>::upd(eb[4], nE, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                     none)))
+        return st;
+    // Step 5 on I1 u I2, and F from the surrogate
+    nn::iface_combine<T>((T*)s->accH, (T*)s->accU, cb[5] - cb[3], eb[4] - eb[2], L, dt / M, cb[3],
+                         eb[2], Sh, Su, Ah, Au, s->s);
+    SCHK(s, hipMemcpyAsync(Ah, Ph, s->nF * sizeof(T), hipMemcpyDeviceToDevice, s->s));
+    SCHK(s, hipMemcpyAsync(Au, Pu, s->nFe * sizeof(T), hipMemcpyDeviceToDevice, s->s));
+    nn::mass_fix<T>(dm.area, Sh, Ah, nC, s->nF, s->inv_area_f, s->mpart, s->mshift, s->s);
+    // R(x_new) on F and the residual sums
     if ((st = fine_rhs<T>(s, Ah, Au, R1h, R1u))) return st;
-    nn::gate_sums<T>((const T*)s->Sh, (const T*)s->Su, Ah, Au, R0h, R0u, R1h, R1u, s->nF, s->nFe,
-                     dt, s->dpart, s->gout, s->s);
+    nn::gate_sums<T>((const T*)Sh, (const T*)Su, Ah, Au, R0h, R0u, R1h, R1u, s->nF, s->nFe, dt,
+                     s->dpart, s->gout, s->s);
     return LTS_OK;
 }
 
 template <typename T>
-lts_status capture_step(lts_sur* s, double dt) {
+lts_status capture_step(lts_sur* s, double dt, int M) {
     lts_ctx* c = s->c;
-    if (s->gexec && s->g_dt == dt) return LTS_OK;
+    if (s->gexec && s->g_dt == dt && s->g_M == M) return LTS_OK;
+    lts_status st0 = stage_buffers<T>(s, M);
+    if (st0) return st0;
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     s->gexec = nullptr;
@@ -299,7 +461,7 @@ lts_status capture_step(lts_sur* s, double dt) {
     int* saved = c->flag;
     c->flag = s->flag;
     SCHK(s, hipStreamBeginCapture(s->s, hipStreamCaptureModeThreadLocal));
-    lts_status st = enqueue_sur_step<T>(s, dt);
+    lts_status st = enqueue_sur_step<T>(s, dt, M);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(s->s, &gr);
     c->flag = saved;
@@ -311,6 +473,7 @@ lts_status capture_step(lts_sur* s, double dt) {
     s->graph = gr;
     SCHK(s, hipGraphInstantiate(&s->gexec, gr, nullptr, nullptr, 0));
     s->g_dt = dt;
+    s->g_M = M;
     return LTS_OK;
 }
 
@@ -319,7 +482,7 @@ lts_status sur_step_typed(lts_sur* s, double dt, int M, int n, double tau, int m
                           int* n_acc, double* resid) {
     lts_ctx* c = s->c;
     lts_status st;
-    if ((st = capture_step<T>(s, dt))) return st;
+    if ((st = capture_step<T>(s, dt, M))) return st;
     int acc = 0;
     for (int k = 0; k < n; ++k) {
         if (s->skip > 0) {  // backing off after a rejection: plain LTS3

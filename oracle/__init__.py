@@ -70,6 +70,9 @@ def _load(omp: bool = False):
     lib.om_rk4_step.argtypes = [P, f64p, f64p, cd]
     lib.om_lts_step.argtypes = [P, ci, i8p, i8p, u8p, u8p, f64p, f64p, cd, ci]
     lib.om_lts_predict_coeffs.argtypes = [ci, ci, ci, ci, f64p]
+    lib.om_mlts_regions.argtypes = [P, ci, u8p, ci, ci, i8p, i8p, u8p, u8p]
+    lib.om_mlts_regions.restype = ci
+    lib.om_mlts_step.argtypes = [P, ci, i8p, i8p, u8p, u8p, i32p, f64p, f64p, cd]
     lib.om_set_reading.argtypes = [ci]
     lib.om_get_reading.restype = ci
     lib.om_diagnostics.argtypes = [P, f64p, f64p, ctypes.POINTER(cd), ctypes.POINTER(cd)]
@@ -206,6 +209,39 @@ class Oracle:
         for _ in range(n):
             self._lib.om_lts_step(self._h, order, r.cell, r.edge, r.cell_fbar,
                                   r.edge_fbar, h, u, float(dt), int(M))
+        return h, u
+
+    def ml_regions(self, masks, n1: int = 2, n2: int = 2) -> Regions:
+        """Labels of every level of a multi-level LTS3 (Remark 3.1): masks is
+        a list of nested fine masks, outermost first; the Regions arrays hold
+        one row per level.  Raises when a level is unusable or not nested at
+        least three cell rings inside the previous one."""
+        m = self.mesh
+        fm = np.ascontiguousarray(np.stack([np.asarray(x, np.uint8) for x in masks]))
+        nl = fm.shape[0]
+        cr = np.empty((nl, m.nCells), np.int8)
+        er = np.empty((nl, m.nEdges), np.int8)
+        cf = np.empty((nl, m.nCells), np.uint8)
+        ef = np.empty((nl, m.nEdges), np.uint8)
+        rc = self._lib.om_mlts_regions(self._h, nl + 1, fm.reshape(-1), int(n1), int(n2),
+                                       cr.reshape(-1), er.reshape(-1), cf.reshape(-1),
+                                       ef.reshape(-1))
+        if rc != 0:
+            raise ValueError("unusable or insufficiently nested LTS levels")
+        return Regions(cr, er, cf, ef)
+
+    def mlts(self, h, u, dt: float, Ms, regions: Regions, n: int = 1):
+        """n coarse steps of multi-level LTS3: Ms[l] is the step ratio of level
+        l to level l+1 (len(Ms) = number of fine regions)."""
+        h = np.array(h, np.float64)
+        u = np.array(u, np.float64)
+        r = regions
+        Ma = np.ascontiguousarray(Ms, np.int32)
+        assert r.cell.ndim == 2 and Ma.shape[0] == r.cell.shape[0]
+        for _ in range(n):
+            self._lib.om_mlts_step(self._h, Ma.shape[0] + 1, r.cell.reshape(-1),
+                                   r.edge.reshape(-1), r.cell_fbar.reshape(-1),
+                                   r.edge_fbar.reshape(-1), Ma, h, u, float(dt))
         return h, u
 
     def diagnostics(self, h, u):

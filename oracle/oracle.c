@@ -599,6 +599,237 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *creg,
 }
 
 /* ------------------------------------------------------------------------ */
+/* More than two LTS levels (Remark 3.1): nested fine regions with an integer */
+/* step ratio between neighbouring levels.                                   */
+/*
+   Level 0 is Algorithm 2.2 (LTS3) on the whole mesh with fine region F_0 and
+   ratio M[0].  The fine substeps of level l (size dt_l / M[l]) are not
+   SSPRK3 stages but LTS3 steps of level l+1 on the domain D_{l+1} = F_l, with
+   fine region F_{l+1} inside F_l and ratio M[l+1]; the deepest level takes
+   plain SSPRK3 substeps.  Every level's Steps 1, 2 and 4 evaluate the
+   right-hand side on the whole mesh, with the values outside its domain held
+   at the enclosing level's stage of the same index (the enclosing interface 1
+   predicted, its interface 2 and coarse region at the coarse stage).  Those
+   same evaluations give the enclosing level's interface accumulation
+   (Steps 3.s.2): near the enclosing interface the domain's cells are coarse
+   cells of the inner level, whose three coarse stages are exactly SSPRK3
+   stages of the enclosing fine step.  This needs every inner fine and
+   interface cell to lie at least three cell rings inside the domain
+   (om_mlts_regions checks it).  Labels of level l: creg[l*nC + i],
+   ereg[l*nE + e], cfbar, efbar as om_regions gives them for F_l. */
+
+typedef struct {
+    int nlev;              /* LTS levels (fine regions + 1) */
+    const int8_t *creg, *ereg;
+    const uint8_t *cfbar, *efbar;
+    const int *M;          /* M[l]: step ratio of level l to level l+1 */
+} ml_levels;
+
+static int ml_in_domain_cell(const om_ctx *c, const ml_levels *L, int l, int i) {
+    return l == 0 || L->creg[(size_t)(l - 1) * c->nC + i] == OM_F;
+}
+static int ml_in_domain_edge(const om_ctx *c, const ml_levels *L, int l, int e) {
+    return l == 0 || L->ereg[(size_t)(l - 1) * c->nE + e] == OM_F;
+}
+/* the enclosing level's interface (I1 u I2 of level l-1) */
+static int ml_outer_iface_cell(const om_ctx *c, const ml_levels *L, int l, int i) {
+    if (l == 0) return 0;
+    int r = L->creg[(size_t)(l - 1) * c->nC + i];
+    return r == OM_I1 || r == OM_I2;
+}
+static int ml_outer_iface_edge(const om_ctx *c, const ml_levels *L, int l, int e) {
+    if (l == 0) return 0;
+    int r = L->ereg[(size_t)(l - 1) * c->nE + e];
+    return r == OM_I1 || r == OM_I2;
+}
+
+/* One LTS3 step of size dt on level l's domain.  xh[s], xu[s] (s = 0, 1, 2)
+   are full-mesh arrays.  On entry xh[0], xu[0] hold the step's start values on
+   the domain; outside the domain xh[s], xu[s] hold the enclosing level's
+   values at this step's stage s.  On return xh[0], xu[0] hold the end values
+   on the domain (xh[1..2], xu[1..2] are overwritten on the domain).  aH[s],
+   aU[s] (NULL at level 0): the enclosing level's interface accumulators, to
+   which the right-hand side of this step's stage s is added. */
+static void ml_step(const om_ctx *c, const ml_levels *L, int l, double dt,
+                    double *xh[3], double *xu[3], double *aH[3], double *aU[3]) {
+    int nC = c->nC, nE = c->nE, M = L->M[l];
+    size_t bc = sizeof(double) * nC, be = sizeof(double) * nE;
+    const int8_t *cr = L->creg + (size_t)l * nC, *er = L->ereg + (size_t)l * nE;
+    const uint8_t *cf = L->cfbar + (size_t)l * nC, *ef = L->efbar + (size_t)l * nE;
+    const double th[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+    double delta = dt / M;
+    double *h0 = dup_mem(xh[0], bc), *u0 = dup_mem(xu[0], be);
+    double *dh = malloc(bc), *du = malloc(be);
+
+    /* Step 1: first stage with dt on underlined F, I1, I2, C of this level */
+    om_rhs(c, xh[0], xu[0], dh, du);
+    for (int i = 0; i < nC; ++i) {
+        if (aH && ml_outer_iface_cell(c, L, l, i)) aH[0][i] += dh[i];
+        if (!ml_in_domain_cell(c, L, l, i)) continue;
+        xh[1][i] = (cr[i] != OM_F || cf[i]) ? h0[i] + dt * dh[i] : h0[i];
+    }
+    for (int e = 0; e < nE; ++e) {
+        if (aU && ml_outer_iface_edge(c, L, l, e)) aU[0][e] += du[e];
+        if (!ml_in_domain_edge(c, L, l, e)) continue;
+        xu[1][e] = (er[e] != OM_F || ef[e]) ? u0[e] + dt * du[e] : u0[e];
+    }
+    /* Step 2: second stage with dt on I1, I2, C of this level */
+    om_rhs(c, xh[1], xu[1], dh, du);
+    for (int i = 0; i < nC; ++i) {
+        if (aH && ml_outer_iface_cell(c, L, l, i)) aH[1][i] += dh[i];
+        if (!ml_in_domain_cell(c, L, l, i)) continue;
+        xh[2][i] = cr[i] != OM_F ? 0.75 * h0[i] + 0.25 * xh[1][i] + 0.25 * dt * dh[i] : h0[i];
+    }
+    for (int e = 0; e < nE; ++e) {
+        if (aU && ml_outer_iface_edge(c, L, l, e)) aU[1][e] += du[e];
+        if (!ml_in_domain_edge(c, L, l, e)) continue;
+        xu[2][e] = er[e] != OM_F ? 0.75 * u0[e] + 0.25 * xu[1][e] + 0.25 * dt * du[e] : u0[e];
+    }
+
+    /* Step 3: M substeps on F of this level.  zh[s], zu[s]: the substep stage
+       states, starting from the coarse stages (so F starts at the step's
+       start values); outside F they keep this level's coarse stage s
+       (interface 1 is predicted per substep). */
+    double *zh[3], *zu[3], *Hacc[3], *Uacc[3];
+    for (int s = 0; s < 3; ++s) {
+        zh[s] = dup_mem(xh[s], bc);
+        zu[s] = dup_mem(xu[s], be);
+        Hacc[s] = calloc(nC, sizeof(double));
+        Uacc[s] = calloc(nE, sizeof(double));
+    }
+    int inner = l + 1 < L->nlev - 1;
+    for (int k = 0; k < M; ++k) {
+        if (inner) {
+            /* interface-1 predictions for the three stages of substep k, then
+               one LTS3 step of the next level on F (its Steps 1, 2 and 4 add
+               this level's accumulation terms) */
+            for (int s = 0; s < 3; ++s) {
+                double q[3];
+                om_lts_predict_coeffs(3, s, k, M, q);
+                for (int i = 0; i < nC; ++i)
+                    if (ml_in_domain_cell(c, L, l, i) && cr[i] == OM_I1)
+                        zh[s][i] = q[0] * h0[i] + q[1] * xh[1][i] + q[2] * xh[2][i];
+                for (int e = 0; e < nE; ++e)
+                    if (ml_in_domain_edge(c, L, l, e) && er[e] == OM_I1)
+                        zu[s][e] = q[0] * u0[e] + q[1] * xu[1][e] + q[2] * xu[2][e];
+            }
+            ml_step(c, L, l + 1, delta, zh, zu, Hacc, Uacc);
+            continue;
+        }
+        for (int s = 0; s < 3; ++s) {
+            /* Step 3.s.1: predict interface 1 */
+            double q[3];
+            om_lts_predict_coeffs(3, s, k, M, q);
+            for (int i = 0; i < nC; ++i)
+                if (ml_in_domain_cell(c, L, l, i) && cr[i] == OM_I1)
+                    zh[s][i] = q[0] * h0[i] + q[1] * xh[1][i] + q[2] * xh[2][i];
+            for (int e = 0; e < nE; ++e)
+                if (ml_in_domain_edge(c, L, l, e) && er[e] == OM_I1)
+                    zu[s][e] = q[0] * u0[e] + q[1] * xu[1][e] + q[2] * xu[2][e];
+            om_rhs(c, zh[s], zu[s], dh, du);
+            /* Step 3.s.2: accumulate on I1 u I2 of this level */
+            for (int i = 0; i < nC; ++i)
+                if (ml_in_domain_cell(c, L, l, i) && (cr[i] == OM_I1 || cr[i] == OM_I2))
+                    Hacc[s][i] += dh[i];
+            for (int e = 0; e < nE; ++e)
+                if (ml_in_domain_edge(c, L, l, e) && (er[e] == OM_I1 || er[e] == OM_I2))
+                    Uacc[s][e] += du[e];
+            /* Step 3.s.3: SSPRK3 stage with dt/M on F of this level */
+            for (int i = 0; i < nC; ++i) {
+                if (cr[i] != OM_F || !ml_in_domain_cell(c, L, l, i)) continue;
+                if (s == 0) zh[1][i] = zh[0][i] + delta * dh[i];
+                else if (s == 1) zh[2][i] = 0.75 * zh[0][i] + 0.25 * zh[1][i] + 0.25 * delta * dh[i];
+                else zh[0][i] = zh[0][i] / 3.0 + 2.0 / 3.0 * zh[2][i] + 2.0 / 3.0 * delta * dh[i];
+            }
+            for (int e = 0; e < nE; ++e) {
+                if (er[e] != OM_F || !ml_in_domain_edge(c, L, l, e)) continue;
+                if (s == 0) zu[1][e] = zu[0][e] + delta * du[e];
+                else if (s == 1) zu[2][e] = 0.75 * zu[0][e] + 0.25 * zu[1][e] + 0.25 * delta * du[e];
+                else zu[0][e] = zu[0][e] / 3.0 + 2.0 / 3.0 * zu[2][e] + 2.0 / 3.0 * delta * du[e];
+            }
+        }
+    }
+
+    /* Step 4: third stage with dt on C of this level */
+    om_rhs(c, xh[2], xu[2], dh, du);
+    for (int i = 0; i < nC; ++i)
+        if (aH && ml_outer_iface_cell(c, L, l, i)) aH[2][i] += dh[i];
+    for (int e = 0; e < nE; ++e)
+        if (aU && ml_outer_iface_edge(c, L, l, e)) aU[2][e] += du[e];
+    /* Step 5 and the new values on the domain */
+    for (int i = 0; i < nC; ++i) {
+        if (!ml_in_domain_cell(c, L, l, i)) continue;
+        if (cr[i] == OM_C)
+            xh[0][i] = h0[i] / 3.0 + 2.0 / 3.0 * xh[2][i] + 2.0 / 3.0 * dt * dh[i];
+        else if (cr[i] == OM_F)
+            xh[0][i] = zh[0][i];
+        else
+            xh[0][i] = h0[i] + delta * (th[0] * Hacc[0][i] + th[1] * Hacc[1][i] + th[2] * Hacc[2][i]);
+    }
+    for (int e = 0; e < nE; ++e) {
+        if (!ml_in_domain_edge(c, L, l, e)) continue;
+        if (er[e] == OM_C)
+            xu[0][e] = u0[e] / 3.0 + 2.0 / 3.0 * xu[2][e] + 2.0 / 3.0 * dt * du[e];
+        else if (er[e] == OM_F)
+            xu[0][e] = zu[0][e];
+        else
+            xu[0][e] = u0[e] + delta * (th[0] * Uacc[0][e] + th[1] * Uacc[1][e] + th[2] * Uacc[2][e]);
+    }
+    free(h0); free(u0); free(dh); free(du);
+    for (int s = 0; s < 3; ++s) {
+        free(zh[s]); free(zu[s]); free(Hacc[s]); free(Uacc[s]);
+    }
+}
+
+void om_mlts_step(const om_ctx *c, int nlev, const int8_t *creg, const int8_t *ereg,
+                  const uint8_t *cfbar, const uint8_t *efbar, const int32_t *M,
+                  double *h, double *u, double dt) {
+    size_t bc = sizeof(double) * c->nC, be = sizeof(double) * c->nE;
+    int Mi[16];
+    for (int l = 0; l < nlev - 1 && l < 16; ++l) Mi[l] = M[l];
+    ml_levels L = {nlev, creg, ereg, cfbar, efbar, Mi};
+    double *xh[3] = {h, dup_mem(h, bc), dup_mem(h, bc)};
+    double *xu[3] = {u, dup_mem(u, be), dup_mem(u, be)};
+    ml_step(c, &L, 0, dt, xh, xu, NULL, NULL);
+    free(xh[1]); free(xh[2]); free(xu[1]); free(xu[2]);
+}
+
+int om_mlts_regions(const om_ctx *c, int nlev, const uint8_t *masks, int n1, int n2,
+                    int8_t *creg, int8_t *ereg, uint8_t *cfbar, uint8_t *efbar) {
+    int nC = c->nC;
+    if (nlev < 2 || nlev > 16) return -1;
+    for (int l = 0; l < nlev - 1; ++l)
+        if (om_regions(c, masks + (size_t)l * nC, n1, n2, creg + (size_t)l * nC,
+                       ereg + (size_t)l * c->nE, cfbar + (size_t)l * nC,
+                       efbar + (size_t)l * c->nE) != 0)
+            return -1;
+    /* nesting: the fine, interface-1 and interface-2 cells of level l lie at
+       least three rings inside F of level l-1 (depth: ring distance from the
+       cells outside it, 0, 1, 2, or -1 for three and more), so every value
+       their right-hand side reads lies inside and the two fine rings next to
+       the enclosing interface 1 are coarse cells of level l */
+    int *depth = (int *)malloc(sizeof(int) * nC);
+    int ok = 1;
+    for (int l = 1; l < nlev - 1 && ok; ++l) {
+        const int8_t *outer = creg + (size_t)(l - 1) * nC, *cr = creg + (size_t)l * nC;
+        for (int i = 0; i < nC; ++i) depth[i] = outer[i] == OM_F ? -1 : 0;
+        for (int r = 1; r <= 2; ++r)
+            for (int i = 0; i < nC; ++i) {
+                if (depth[i] != -1) continue;
+                for (int j = 0; j < c->nEoC[i]; ++j)
+                    if (depth[c->coc[(size_t)i * c->maxE + j]] == r - 1) {
+                        depth[i] = r;
+                        break;
+                    }
+            }
+        for (int i = 0; i < nC; ++i)
+            if (cr[i] != OM_C && depth[i] != -1) ok = 0;
+    }
+    free(depth);
+    return ok ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
 
 static void neumaier_add(double *sum, double *comp, double x) {
     double t = *sum + x;

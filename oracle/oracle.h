@@ -86,6 +86,23 @@ void om_lts_step(const om_ctx *c, int order, const int8_t *cell_region,
                  const uint8_t *edge_fbar, double *h, double *u,
                  double dt, int M);
 
+/* More than two LTS levels (Remark 3.1), LTS3 only.  nlev >= 2 levels; level
+   l < nlev - 1 has the fine region masks[l*nCells ...] (nested: each inside
+   the previous one) and the step ratio M[l] to level l+1.  om_mlts_regions
+   labels every level (arrays of nlev-1 blocks of nCells / nEdges entries, as
+   om_regions) and returns -1 unless every fine, interface-1 and interface-2
+   cell of level l >= 1 lies at least three cell rings inside the fine region
+   of level l-1.  om_mlts_step advances one coarse step dt in place: level l's
+   fine substeps are LTS3 steps of level l+1 (see oracle.c); with nlev = 2 it
+   is om_lts_step of order 3. */
+int om_mlts_regions(const om_ctx *c, int nlev, const uint8_t *masks, int n1, int n2,
+                    int8_t *cell_region, int8_t *edge_region, uint8_t *cell_fbar,
+                    uint8_t *edge_fbar);
+void om_mlts_step(const om_ctx *c, int nlev, const int8_t *cell_region,
+                  const int8_t *edge_region, const uint8_t *cell_fbar,
+                  const uint8_t *edge_fbar, const int32_t *M, double *h, double *u,
+                  double dt);
+
 /* Interface-1 prediction coefficients (a, b, c) such that the predicted value
    is a*x_old + b*x_1st + c*x_2nd, for stage s in {0,1,2} of fine substep k. */
 void om_lts_predict_coeffs(int order, int stage, int k, int M, double out[3]);

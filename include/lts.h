@@ -58,6 +58,7 @@ typedef enum { LTS_C = 0, LTS_I2 = 1, LTS_I1 = 2, LTS_F = 3 } lts_region;
 /* Largest number of edges a cell may have: the slot capacity of the cell
    kernels (8 lanes per cell up to 8 edges, 16 lanes above). */
 #define LTS_MAX_EDGES 16
+#define LTS_MAX_LEVELS 8  /* LTS levels of lts_upload_mesh_levels (fine levels + 1) */
 
 typedef struct lts_ctx lts_ctx;
 
@@ -134,6 +135,37 @@ lts_status lts_set_layers(lts_ctx *ctx, int n_layers);
    Replaces any previous mesh and invalidates the state. */
 lts_status lts_upload_mesh(lts_ctx *ctx, const lts_mesh *mesh, const uint8_t *fine_mask,
                            int n_if1_rings, int n_if2_rings, double gravity);
+
+/* More than two LTS levels (Remark 3.1: regions of several resolutions,
+   each neighbouring pair with an integer step ratio).  fine_masks holds
+   n_fine_levels nested masks of n_cells bytes one after another, outermost
+   first: level l's fine region F_l = cells with fine_masks[l][i] != 0, each
+   labelled as lts_upload_mesh labels one fine region (n_if1_rings and
+   n_if2_rings interface rings at every level).  Every fine, interface-1 and
+   interface-2 cell of level l >= 1 must lie at least four cell rings inside
+   F_{l-1} (LTS_ELABEL otherwise: three rings are what the method needs, the
+   fourth keeps every level's evaluation sets contiguous in device order).
+   n_fine_levels = 1 is lts_upload_mesh; more than one needs a single-layer
+   context.  Level 0's labels are the ones lts_get_regions and
+   lts_region_counts report, and lts_step runs the two-level scheme on them. */
+lts_status lts_upload_mesh_levels(lts_ctx *ctx, const lts_mesh *mesh, int n_fine_levels,
+                                  const uint8_t *fine_masks, int n_if1_rings, int n_if2_rings,
+                                  double gravity);
+
+/* Labels of level `level` (0 .. n_fine_levels - 1), as lts_get_regions. */
+lts_status lts_get_level_regions(lts_ctx *ctx, int level, int8_t *cell_region,
+                                 int8_t *edge_region, uint8_t *cell_fbar, uint8_t *edge_fbar);
+
+/* Advance n_steps coarse steps of multi-level LTS3 on a mesh uploaded with
+   lts_upload_mesh_levels: M[l] (l = 0 .. n_fine_levels - 1, each >= 1) is the
+   step ratio of level l to level l+1.  Level l's M[l] fine substeps on F_l
+   are LTS3 steps of level l+1 (the deepest level takes SSPRK3 substeps);
+   each level's Steps 1, 2 and 4 also evaluate the enclosing level's
+   interface, which accumulates those right-hand sides (Steps 3.s.2) for its
+   correction (Step 5).  Conserves mass exactly; the innermost fine cells
+   take steps of dt_coarse / (M[0] M[1] ... M[n_fine_levels - 1]).  Asynchronous.
+   LTS_EINVAL for a two-level mesh, a NULL M, a ratio < 1 or dt_coarse <= 0. */
+lts_status lts_step_levels(lts_ctx *ctx, double dt_coarse, const int32_t *M, int n_steps);
 
 /* Region labels in the caller's numbering (host arrays, any may be NULL). */
 lts_status lts_get_regions(lts_ctx *ctx, int8_t *cell_region, int8_t *edge_region,
@@ -215,6 +247,20 @@ lts_status lts_plan(const lts_mesh *mesh, const uint8_t *fine_mask, int n_if1_ri
                     uint8_t *cell_fbar, uint8_t *edge_fbar, int32_t *cell_order,
                     int32_t *edge_order, int32_t *vertex_order, int32_t *ranges,
                     char *errbuf, int errlen);
+
+/* Host-only planning of a multi-level mesh (no device needed): the device
+   ordering and, per level l (0 .. n_fine_levels - 1), 46 int32 ranges:
+   cell class starts [8] (F interior, F2, F1, I1, I2, C1, rest of C, end of
+   the level's domain), edge class starts [6] (F-interior edges, underlined-F
+   edges, I1, I2, C, end of the domain), then four passes (Steps 1, 2, 3, 4;
+   Steps 1, 2 and 4 of level l >= 1 also target level l-1's interface) of 8
+   entries each: cell kernel range, vertex range, target cells, target
+   edges (lo, hi pairs).  fine_masks, rings and errors as
+   lts_upload_mesh_levels; errbuf receives the message. */
+lts_status lts_plan_levels(const lts_mesh *mesh, int n_fine_levels, const uint8_t *fine_masks,
+                           int n_if1_rings, int n_if2_rings, int32_t *cell_order,
+                           int32_t *edge_order, int32_t *vertex_order, int32_t *ranges,
+                           char *errbuf, int errlen);
 
 const char *lts_last_error(const lts_ctx *ctx);
 void lts_destroy(lts_ctx *ctx);

@@ -442,6 +442,23 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
         (s = dalloc(c, &c->acch, nIc * ts)) || (s = dalloc(c, &c->accu, nIe * ts)) ||
         (s = dalloc(c, &c->zs, 2 * (size_t)nE * ts)) || (s = dalloc(c, &c->q, nV * ts)))
         return s;
+    // multi-level LTS3: level 0 uses the buffers above, inner levels their own
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        LevelData& V = c->lv[l];
+        if (l == 0) {
+            V.x0h = c->x0h; V.x1h = c->x1h; V.x2h = c->x2h;
+            V.x0u = c->x0u; V.x1u = c->x1u; V.x2u = c->x2u;
+            V.acch = c->acch; V.accu = c->accu;
+            continue;
+        }
+        const size_t i1c = V.cb[4] - V.cb[3], i1e = V.eb[3] - V.eb[2];
+        const size_t ic = V.cb[5] - V.cb[3], ie = V.eb[4] - V.eb[2];
+        if ((s = dalloc(c, &V.x0h, i1c * ts)) || (s = dalloc(c, &V.x1h, i1c * ts)) ||
+            (s = dalloc(c, &V.x2h, i1c * ts)) || (s = dalloc(c, &V.x0u, i1e * ts)) ||
+            (s = dalloc(c, &V.x1u, i1e * ts)) || (s = dalloc(c, &V.x2u, i1e * ts)) ||
+            (s = dalloc(c, &V.acch, ic * ts)) || (s = dalloc(c, &V.accu, ie * ts)))
+            return s;
+    }
     void* fp = nullptr;
     if ((s = dalloc(c, &fp, 64))) return s;
     c->flag = static_cast<int*>(fp);
@@ -547,6 +564,25 @@ void make_plans(lts_ctx* c, const lts_mesh* m) {
                                 targets[p].et_hi);
     // interface cells and edges only (the surrogate's interface accumulation)
     c->iface_plan = plan_cover(c, m, cb[3], cb[5], eb[2], eb[4]);
+    // multi-level LTS3: level 0 is the two-level plan; level l >= 1 adds the
+    // enclosing interface (accumulated) to its Steps 1, 2 and 4
+    if (!c->lv.empty()) {
+        LevelData& V0 = c->lv[0];
+        std::copy(cb, cb + 8, V0.cb);
+        std::copy(eb, eb + 6, V0.eb);
+        V0.p1 = c->plan[P_STEP1];
+        V0.p2 = c->plan[P_STEP2];
+        V0.p3 = c->plan[P_STEP3];
+        V0.p4 = c->plan[P_STEP4];
+        for (size_t l = 1; l < c->lv.size(); ++l) {
+            LevelData& V = c->lv[l];
+            const LevelData& O = c->lv[l - 1];
+            V.p1 = plan_cover(c, m, V.cb[1], O.cb[5], V.eb[1], O.eb[4]);
+            V.p2 = plan_cover(c, m, V.cb[3], O.cb[5], V.eb[2], O.eb[4]);
+            V.p3 = plan_cover(c, m, 0, V.cb[5], 0, V.eb[4]);
+            V.p4 = plan_cover(c, m, V.cb[5], O.cb[5], V.eb[4], O.eb[4]);
+        }
+    }
 }
 
 // Enqueue n steps of `scheme`: replayed from a hipGraph captured once per
@@ -562,7 +598,8 @@ lts_status run_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
         }
         return LTS_OK;
     }
-    if (!(c->gexec && c->g_kind == scheme && c->g_M == M && c->g_dt == dt)) {
+    if (!(c->gexec && c->g_kind == scheme && c->g_M == M && c->g_dt == dt &&
+          (scheme != SCH_MLTS3 || c->g_Ms == c->run_Ms))) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         c->gexec = nullptr;
@@ -581,6 +618,7 @@ lts_status run_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
         HIPCHK(c, hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
         c->g_kind = scheme;
         c->g_M = M;
+        c->g_Ms = c->run_Ms;
         c->g_dt = dt;
     }
     for (int i = 0; i < n; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
@@ -752,12 +790,80 @@ namespace {
 
 // Host-side planning: validation, LTS labels, permutation, pass plans.
 lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1, int n2,
-                     double gravity) {
+                     double gravity, int nfine = 1) {
     lts_status s = validate(c, m);
     if (s) return s;
     std::vector<int> cls, ecls;
     if ((s = label_regions(c, m, fine, n1, n2, cls, ecls))) return s;
     const int nC = m->n_cells, nE = m->n_edges, nV = m->n_vertices;
+    // multi-level LTS3: the classes of every nested level (level 0 above)
+    c->lv.clear();
+    std::vector<std::vector<int>> lcls(nfine), lecls(nfine);
+    lcls[0] = cls;
+    lecls[0] = ecls;
+    if (nfine > 1) {
+        c->lv.resize(nfine);
+        for (int l = 1; l < nfine; ++l) {
+            lts_ctx tmp;
+            if ((s = label_regions(&tmp, m, fine + (size_t)l * nC, n1, n2, lcls[l], lecls[l])))
+                return fail(c, s, "level " + std::to_string(l) + ": " + tmp.err);
+            LevelData& V = c->lv[l];
+            V.creg = tmp.creg;
+            V.ereg = tmp.ereg;
+            V.cfbar = tmp.cfbar;
+            V.efbar = tmp.efbar;
+            // nesting: level l's fine and interface cells lie at least four
+            // cell rings inside level l-1's fine region (three would do for
+            // the method; the fourth keeps level l's coarse cells next to its
+            // interface 2 inside level l-1's interior class, so every level's
+            // evaluation sets stay contiguous ranges)
+            const std::vector<int8_t>& outer = l == 1 ? c->creg : c->lv[l - 1].creg;
+            std::vector<int> depth(nC, -1);
+            for (int i = 0; i < nC; ++i)
+                if (outer[i] != LTS_F) depth[i] = 0;
+            for (int r = 1; r <= 3; ++r)
+                for (int i = 0; i < nC; ++i) {
+                    if (depth[i] != -1) continue;
+                    for (int j = 0; j < m->n_edges_on_cell[i]; ++j)
+                        if (depth[m->cells_on_cell[(size_t)i * m->max_edges + j]] == r - 1) {
+                            depth[i] = r;
+                            break;
+                        }
+                }
+            for (int i = 0; i < nC; ++i)
+                if (V.creg[i] != LTS_C && depth[i] != -1)
+                    return fail(c, LTS_ELABEL,
+                                "level " + std::to_string(l) +
+                                    ": a fine or interface cell lies fewer than four rings "
+                                    "inside the enclosing fine region");
+        }
+        c->lv[0].creg = c->creg;
+        c->lv[0].ereg = c->ereg;
+        c->lv[0].cfbar = c->cfbar;
+        c->lv[0].efbar = c->efbar;
+        // sort keys: level 0's class, then each inner level's class while all
+        // enclosing classes are 0 (the interior of their fine region)
+        for (int i = 0; i < nC; ++i) {
+            int key = 0;
+            bool inside = true;
+            for (int l = 0; l < nfine; ++l) {
+                const int k = inside ? lcls[l][i] : 0;
+                key = key * 8 + k;
+                inside = inside && lcls[l][i] == 0;
+            }
+            cls[i] = key;
+        }
+        for (int e = 0; e < nE; ++e) {
+            int key = 0;
+            bool inside = true;
+            for (int l = 0; l < nfine; ++l) {
+                const int k = inside ? lecls[l][e] : 0;
+                key = key * 8 + k;
+                inside = inside && lecls[l][e] == 0;
+            }
+            ecls[e] = key;
+        }
+    }
     c->nC = nC;
     c->nE = nE;
     c->nV = nV;
@@ -793,10 +899,25 @@ lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1,
     });
     c->cinv.assign(nC, 0);
     for (int ni = 0; ni < nC; ++ni) c->cinv[c->cperm[ni]] = ni;
-    for (int k = 0; k < 8; ++k) c->cb[k] = nC;
-    for (int ni = nC - 1; ni >= 0; --ni) c->cb[cls[c->cperm[ni]]] = ni;
-    for (int k = 6; k >= 0; --k) c->cb[k] = std::min(c->cb[k], c->cb[k + 1]);
-    c->cb[7] = nC;
+    // class starts of level 0, then of every inner level inside the interior
+    // of the enclosing fine region
+    auto starts = [&](const std::vector<int>& lc, int lo, int hi, int* out, int nk) {
+        for (int k = 0; k < nk; ++k) out[k] = hi;
+        for (int ni = hi - 1; ni >= lo; --ni) out[lc[ni]] = ni;
+        for (int k = nk - 2; k >= 0; --k) out[k] = std::min(out[k], out[k + 1]);
+    };
+    {
+        std::vector<int> lc(nC);
+        for (int ni = 0; ni < nC; ++ni) lc[ni] = lcls[0][c->cperm[ni]];
+        starts(lc, 0, nC, c->cb, 7);
+        c->cb[7] = nC;
+        for (int l = 1; l < nfine; ++l) {
+            int* ob = l == 1 ? c->cb : c->lv[l - 1].cb;
+            for (int ni = 0; ni < nC; ++ni) lc[ni] = lcls[l][c->cperm[ni]];
+            starts(lc, 0, ob[1], c->lv[l].cb, 7);
+            c->lv[l].cb[7] = ob[3];
+        }
+    }
     // edges: class, then (min cell position, max cell position)
     c->eperm.resize(nE);
     std::iota(c->eperm.begin(), c->eperm.end(), 0);
@@ -809,10 +930,18 @@ lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1,
     });
     c->einv.assign(nE, 0);
     for (int ne = 0; ne < nE; ++ne) c->einv[c->eperm[ne]] = ne;
-    for (int k = 0; k < 6; ++k) c->eb[k] = nE;
-    for (int ne = nE - 1; ne >= 0; --ne) c->eb[ecls[c->eperm[ne]]] = ne;
-    for (int k = 4; k >= 0; --k) c->eb[k] = std::min(c->eb[k], c->eb[k + 1]);
-    c->eb[5] = nE;
+    {
+        std::vector<int> lc(nE);
+        for (int ne = 0; ne < nE; ++ne) lc[ne] = lecls[0][c->eperm[ne]];
+        starts(lc, 0, nE, c->eb, 5);
+        c->eb[5] = nE;
+        for (int l = 1; l < nfine; ++l) {
+            int* ob = l == 1 ? c->eb : c->lv[l - 1].eb;
+            for (int ne = 0; ne < nE; ++ne) lc[ne] = lecls[l][c->eperm[ne]];
+            starts(lc, 0, ob[1], c->lv[l].eb, 5);
+            c->lv[l].eb[5] = ob[2];
+        }
+    }
     // vertices: smallest then largest position of their cells
     std::vector<int> vmin(nV), vmax(nV);
     for (int v = 0; v < nV; ++v) {
@@ -843,12 +972,21 @@ extern "C" {
 
 lts_status lts_upload_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1, int n2,
                            double gravity) {
+    return lts_upload_mesh_levels(c, m, 1, fine, n1, n2, gravity);
+}
+
+lts_status lts_upload_mesh_levels(lts_ctx* c, const lts_mesh* m, int nfine, const uint8_t* fine,
+                                  int n1, int n2, double gravity) {
     if (!c || !m || !fine) return c ? fail(c, LTS_EINVAL, "NULL argument") : LTS_EINVAL;
+    if (nfine < 1 || nfine > LTS_MAX_LEVELS - 1)
+        return fail(c, LTS_EINVAL, "n_fine_levels must be 1 .. LTS_MAX_LEVELS - 1");
+    if (nfine > 1 && c->L != 1)
+        return fail(c, LTS_EINVAL, "more than one fine level needs a single-layer context");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LTS_EDEVICE, "hipSetDevice");
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_device(c);
     c->has_mesh = c->has_state = c->nonfinite = false;
-    lts_status s = plan_mesh(c, m, fine, n1, n2, gravity);
+    lts_status s = plan_mesh(c, m, fine, n1, n2, gravity, nfine);
     if (s) return s;
     s = c->prec == LTS_FP64 ? build_device<double>(c, m) : build_device<float>(c, m);
     if (s) {
@@ -888,6 +1026,48 @@ lts_status lts_plan(const lts_mesh* m, const uint8_t* fine, int n1, int n2, int8
             const PassPlan& P = tmp.plan[p];
             const int v[8] = {P.c_lo, P.c_hi, P.v_lo, P.v_hi, P.ct_lo, P.ct_hi, P.et_lo, P.et_hi};
             for (int j = 0; j < 8; ++j) ranges[k++] = v[j];
+        }
+    }
+    return LTS_OK;
+}
+
+lts_status lts_plan_levels(const lts_mesh* m, int nfine, const uint8_t* fine, int n1, int n2,
+                           int32_t* cell_order, int32_t* edge_order, int32_t* vertex_order,
+                           int32_t* ranges, char* errbuf, int errlen) {
+    if (!m || !fine || nfine < 1 || nfine > LTS_MAX_LEVELS - 1) return LTS_EINVAL;
+    lts_ctx tmp;
+    lts_status s = plan_mesh(&tmp, m, fine, n1, n2, 9.81, nfine);
+    if (s) {
+        if (errbuf && errlen > 0) {
+            std::strncpy(errbuf, tmp.err.c_str(), errlen - 1);
+            errbuf[errlen - 1] = 0;
+        }
+        return s;
+    }
+    if (cell_order) std::copy(tmp.cperm.begin(), tmp.cperm.end(), cell_order);
+    if (edge_order) std::copy(tmp.eperm.begin(), tmp.eperm.end(), edge_order);
+    if (vertex_order) std::copy(tmp.vperm.begin(), tmp.vperm.end(), vertex_order);
+    if (ranges) {
+        int k = 0;
+        for (int l = 0; l < nfine; ++l) {
+            LevelData V;
+            if (tmp.lv.empty()) {  // one fine level: the two-level plan
+                std::copy(tmp.cb, tmp.cb + 8, V.cb);
+                std::copy(tmp.eb, tmp.eb + 6, V.eb);
+                V.p1 = tmp.plan[P_STEP1];
+                V.p2 = tmp.plan[P_STEP2];
+                V.p3 = tmp.plan[P_STEP3];
+                V.p4 = tmp.plan[P_STEP4];
+            } else {
+                V = tmp.lv[l];
+            }
+            for (int j = 0; j < 8; ++j) ranges[k++] = V.cb[j];
+            for (int j = 0; j < 6; ++j) ranges[k++] = V.eb[j];
+            for (const PassPlan* P : {&V.p1, &V.p2, &V.p3, &V.p4}) {
+                const int v[8] = {P->c_lo, P->c_hi, P->v_lo, P->v_hi,
+                                  P->ct_lo, P->ct_hi, P->et_lo, P->et_hi};
+                for (int j = 0; j < 8; ++j) ranges[k++] = v[j];
+            }
         }
     }
     return LTS_OK;
@@ -960,11 +1140,14 @@ lts_status lts_init_state_device(lts_ctx* c, const void* dh, const void* du, dou
     return lts_init_state(c, h.data(), u.data(), t0);
 }
 
-lts_status lts_step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
+}  // extern "C"
+
+namespace {
+
+lts_status step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     lts_status s = ready(c, true);
     if (s) return s;
-    if (scheme < SCH_LTS3 || scheme > SCH_RK4) return fail(c, LTS_EINVAL, "unknown scheme");
-    if (scheme >= SCH_SSPRK3) M = 1;
+    if (scheme >= SCH_SSPRK3 && scheme <= SCH_RK4) M = 1;
     if (!(dt > 0) || M < 1 || n < 0) return fail(c, LTS_EINVAL, "need dt > 0, M >= 1, n >= 0");
     if (c->nonfinite) return fail(c, LTS_ENONFINITE, "state is non-finite; re-initialise");
     if (n == 0) return LTS_OK;
@@ -982,8 +1165,46 @@ lts_status lts_step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
     return LTS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+lts_status lts_step_scheme(lts_ctx* c, int scheme, double dt, int M, int n) {
+    if (c && (scheme < SCH_LTS3 || scheme > SCH_RK4)) return fail(c, LTS_EINVAL, "unknown scheme");
+    return step_scheme(c, scheme, dt, M, n);
+}
+
 lts_status lts_step(lts_ctx* c, double dt, int M, int n) {
     return lts_step_scheme(c, SCH_LTS3, dt, M, n);
+}
+
+lts_status lts_step_levels(lts_ctx* c, double dt, const int32_t* M, int n) {
+    if (!c) return LTS_EINVAL;
+    if (!c->has_mesh) return fail(c, LTS_ESTATE, "no mesh");
+    if (c->lv.empty()) return fail(c, LTS_EINVAL, "the mesh was uploaded with one fine level");
+    if (!M) return fail(c, LTS_EINVAL, "NULL ratios");
+    std::vector<int> Ms(c->lv.size());
+    for (size_t l = 0; l < Ms.size(); ++l) {
+        if (M[l] < 1) return fail(c, LTS_EINVAL, "every ratio must be >= 1");
+        Ms[l] = M[l];
+    }
+    c->run_Ms = Ms;
+    return step_scheme(c, SCH_MLTS3, dt, Ms[0], n);
+}
+
+lts_status lts_get_level_regions(lts_ctx* c, int level, int8_t* cr, int8_t* er, uint8_t* cf,
+                                 uint8_t* ef) {
+    lts_status s = ready(c, false);
+    if (s) return s;
+    if (level == 0) return lts_get_regions(c, cr, er, cf, ef);
+    if (level < 0 || level >= (int)c->lv.size())
+        return fail(c, LTS_EINVAL, "no such level");
+    const LevelData& V = c->lv[level];
+    if (cr) std::copy(V.creg.begin(), V.creg.end(), cr);
+    if (er) std::copy(V.ereg.begin(), V.ereg.end(), er);
+    if (cf) std::copy(V.cfbar.begin(), V.cfbar.end(), cf);
+    if (ef) std::copy(V.efbar.begin(), V.efbar.end(), ef);
+    return LTS_OK;
 }
 
 lts_status lts_step_rk3(lts_ctx* c, double dt, int n) {

@@ -32,6 +32,21 @@ struct TimedLaunch {
     double bytes;
 };
 
+// One level of a multi-level LTS3 (Remark 3.1).  Level 0 is the whole mesh;
+// level l >= 1 lives in level l-1's fine region, whose interior cells
+// [0, cb_{l-1}[1]) it orders by its own classes (its coarse part then runs on
+// through level l-1's underlined-F cells to cb_{l-1}[3]).
+struct LevelData {
+    int cb[8] = {0};  // cell class starts inside the level's domain, cb[7]: domain end
+    int eb[6] = {0};  // edge class starts, eb[5]: domain end
+    PassPlan p1, p2, p3, p4;  // Steps 1, 2, 4 (with the enclosing accumulation), Step 3
+    void *x0h = nullptr, *x1h = nullptr, *x2h = nullptr;  // interface-1 copies
+    void *x0u = nullptr, *x1u = nullptr, *x2u = nullptr;
+    void *acch = nullptr, *accu = nullptr;                 // interface accumulators
+    std::vector<int8_t> creg, ereg;                        // caller numbering
+    std::vector<uint8_t> cfbar, efbar;
+};
+
 }  // namespace lts
 
 struct lts_ctx {
@@ -52,6 +67,9 @@ struct lts_ctx {
     int eb[6] = {0};  // edge class starts: Fint Fbar I1 I2 C end
     lts::PassPlan plan[lts::P_N];
     lts::PassPlan iface_plan;  // targets I1 u I2 (cells and edges) only
+    // multi-level LTS3: levels 0 .. lv.size()-1 (empty for a two-level mesh)
+    std::vector<lts::LevelData> lv;
+    std::vector<int> run_Ms, g_Ms;  // step ratios of the run / of the cached graph
 
     // device memory (typed by prec); all owned
     std::vector<void*> allocs;
@@ -189,7 +207,14 @@ struct Run {
             rec->push_back(PassRecord<T>{p, h, u, cs0, cs1, es0, es1, aux});
             return LTS_OK;
         }
-        const PassPlan& P = c->plan[p];
+        return pass_plan(c->plan[p], h, u, cs0, cs1, es0, es1, aux);
+    }
+
+    // The same with an explicit plan and up to two appended element-wise jobs
+    // (aux2: single-layer contexts only).
+    lts_status pass_plan(const PassPlan& P, const T* h, const T* u, const Seg<T>& cs0,
+                         const Seg<T>& cs1, const Seg<T>& es0, const Seg<T>& es1,
+                         const Aux<T>& aux, const Aux<T>& aux2 = Aux<T>()) {
         T* q = static_cast<T*>(c->q);
         T* zs = static_cast<T*>(c->zs);
         hipEvent_t e0, e1;
@@ -219,8 +244,11 @@ struct Run {
         done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux));
         // edge tendency (+ appended element-wise job)
         if ((st = events(&e0, &e1))) return st;
-        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1));
-        done(KC_EDGE, e0, e1, kernel_bytes<T>(P, KC_EDGE, es0, es1, aux));
+        HIPCHK(c, launch_edge<T>(zs, c->nE, P.et_lo, P.et_hi, es0, es1, aux, c->flag, s, e0, e1,
+                                 aux2));
+        done(KC_EDGE, e0, e1,
+             kernel_bytes<T>(P, KC_EDGE, es0, es1, aux) + kernel_bytes<T>(PassPlan(), KC_EDGE,
+                                                                          Seg<T>(), Seg<T>(), aux2));
         return LTS_OK;
     }
 
@@ -278,6 +306,130 @@ struct Run {
         x.c0 = delta;
         return x;
     }
+    // Level-l forms of predict_aux / correct_aux (multi-level LTS3).
+    Aux<T> predict_aux_level(int l, T* xh, T* xu, int stage, int k, int M) {
+        const LevelData& V = c->lv[l];
+        Aux<T> x;
+        double cf[3];
+        predict_coeffs(stage, k, M, cf, 3);
+        x.kind = 1;
+        x.nh = V.cb[4] - V.cb[3];
+        x.nu = V.eb[3] - V.eb[2];
+        x.lo_h = V.cb[3];
+        x.lo_u = V.eb[2];
+        x.xh = xh;
+        x.xu = xu;
+        x.ah = (T*)V.x0h; x.bh = (T*)V.x1h; x.ch = (T*)V.x2h;
+        x.au = (T*)V.x0u; x.bu = (T*)V.x1u; x.cu = (T*)V.x2u;
+        x.c0 = cf[0]; x.c1 = cf[1]; x.c2 = cf[2];
+        return x;
+    }
+    Aux<T> correct_aux_level(int l, double delta) {
+        const LevelData& V = c->lv[l];
+        Aux<T> x;
+        x.kind = 2;
+        x.nh = V.cb[5] - V.cb[3];
+        x.nu = V.eb[4] - V.eb[2];
+        x.nbh = V.cb[4] - V.cb[3];
+        x.nbu = V.eb[3] - V.eb[2];
+        x.lo_h = V.cb[3];
+        x.lo_u = V.eb[2];
+        x.xh = (T*)c->Ah;
+        x.xu = (T*)c->Au;
+        x.ah = (T*)V.x0h; x.bh = (T*)V.acch;
+        x.au = (T*)V.x0u; x.bu = (T*)V.accu;
+        x.c0 = delta;
+        return x;
+    }
+
+    // Multi-level LTS3 (Remark 3.1): one LTS3 step of level l on its domain.
+    // Level l's fine substeps are LTS3 steps of level l+1 (the deepest level
+    // takes SSPRK3 substeps).  For l >= 1 the step is substep k_out of level
+    // l-1: its Steps 1, 2 and 4 also evaluate level l-1's interface (adding
+    // theta_s R to its accumulator) and their edge kernels predict level
+    // l-1's interface 1 for the next stage (stages 1st and 2nd of substep
+    // k_out, then old of substep k_out + 1).
+    lts_status level_step(int l, double dt, const int* Ms, int k_out) {
+        const LevelData& V = c->lv[l];
+        T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
+          *Cu = (T*)c->Cu;
+        const int M = Ms[l];
+        const double delta = dt / M;
+        const int endc = V.cb[7], ende = V.eb[5];
+        const bool deeper = l + 1 < (int)c->lv.size();
+        const double th[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+        const Seg<T> none;
+        auto oacc_c = [&](int st) {
+            if (l == 0) return none;
+            const LevelData& O = c->lv[l - 1];
+            return accum(O.cb[3], O.cb[5], (T*)O.acch, th[st], st == 0 && k_out == 0);
+        };
+        auto oacc_e = [&](int st) {
+            if (l == 0) return none;
+            const LevelData& O = c->lv[l - 1];
+            return accum(O.eb[2], O.eb[4], (T*)O.accu, th[st], st == 0 && k_out == 0);
+        };
+        auto opred = [&](int st, T* xh, T* xu, int k) {
+            if (l == 0) return Aux<T>();
+            return predict_aux_level(l - 1, xh, xu, st, k, Ms[l - 1]);
+        };
+        lts_status st;
+        // Step 1
+        if ((st = pass_plan(V.p1, Ah, Au,
+                            mirror(upd(V.cb[1], endc, Bh, nullptr, 0, Ah, 1, dt), V.cb[3], V.cb[4],
+                                   (T*)V.x1h, (T*)V.x0h),
+                            oacc_c(0),
+                            mirror(upd(V.eb[1], ende, Bu, nullptr, 0, Au, 1, dt), V.eb[2], V.eb[3],
+                                   (T*)V.x1u, (T*)V.x0u),
+                            oacc_e(0), opred(1, Bh, Bu, k_out))))
+            return st;
+        // Step 2
+        if ((st = pass_plan(V.p2, Bh, Bu,
+                            mirror(upd(V.cb[3], endc, Ch, Ah, 0.75, Bh, 0.25, 0.25 * dt), V.cb[3],
+                                   V.cb[4], (T*)V.x2h, nullptr),
+                            oacc_c(1),
+                            mirror(upd(V.eb[2], ende, Cu, Au, 0.75, Bu, 0.25, 0.25 * dt), V.eb[2],
+                                   V.eb[3], (T*)V.x2u, nullptr),
+                            oacc_e(1), opred(2, Ch, Cu, k_out))))
+            return st;
+        // Step 3
+        for (int k = 0; k < M; ++k) {
+            if (deeper) {
+                if ((st = level_step(l + 1, delta, Ms, k))) return st;
+                continue;
+            }
+            T* acch = (T*)V.acch;
+            T* accu = (T*)V.accu;
+            if ((st = pass_plan(V.p3, Ah, Au, upd(0, V.cb[3], Bh, nullptr, 0, Ah, 1, delta),
+                                accum(V.cb[3], V.cb[5], acch, th[0], k == 0),
+                                upd(0, V.eb[2], Bu, nullptr, 0, Au, 1, delta),
+                                accum(V.eb[2], V.eb[4], accu, th[0], k == 0),
+                                predict_aux_level(l, Bh, Bu, 1, k, M))))
+                return st;
+            if ((st = pass_plan(V.p3, Bh, Bu, upd(0, V.cb[3], Ch, Ah, 0.75, Bh, 0.25, 0.25 * delta),
+                                accum(V.cb[3], V.cb[5], acch, th[1], false),
+                                upd(0, V.eb[2], Cu, Au, 0.75, Bu, 0.25, 0.25 * delta),
+                                accum(V.eb[2], V.eb[4], accu, th[1], false),
+                                predict_aux_level(l, Ch, Cu, 2, k, M))))
+                return st;
+            if ((st = pass_plan(V.p3, Ch, Cu,
+                                upd(0, V.cb[3], Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                                accum(V.cb[3], V.cb[5], acch, th[2], false),
+                                upd(0, V.eb[2], Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * delta),
+                                accum(V.eb[2], V.eb[4], accu, th[2], false),
+                                k + 1 < M ? predict_aux_level(l, Ah, Au, 0, k + 1, M) : Aux<T>())))
+                return st;
+        }
+        // Step 4, with Step 5 of this level and the enclosing level's next
+        // stage-old prediction on its edge kernel
+        const Aux<T> next = (l > 0 && k_out + 1 < Ms[l - 1]) ? opred(0, Ah, Au, k_out + 1) : Aux<T>();
+        return pass_plan(V.p4, Ch, Cu,
+                         upd(V.cb[5], endc, Ah, Ah, 1.0 / 3.0, Ch, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                         oacc_c(2),
+                         upd(V.eb[4], ende, Au, Au, 1.0 / 3.0, Cu, 2.0 / 3.0, 2.0 / 3.0 * dt),
+                         oacc_e(2), correct_aux_level(l, delta), next);
+    }
+
     static Seg<T> accum(int lo, int hi, T* acc, double theta, bool first) {
         Seg<T> g;
         g.lo = lo;
@@ -477,11 +629,12 @@ struct Run {
     }
 };
 
-enum { SCH_LTS3 = 0, SCH_LTS2 = 1, SCH_SSPRK3 = 2, SCH_SSPRK2 = 3, SCH_RK4 = 4 };
+enum { SCH_LTS3 = 0, SCH_LTS2 = 1, SCH_SSPRK3 = 2, SCH_SSPRK2 = 3, SCH_RK4 = 4, SCH_MLTS3 = 5 };
 
 template <typename T>
 lts_status one_step(Run<T>& r, int scheme, double dt, int M) {
     switch (scheme) {
+        case SCH_MLTS3: return r.level_step(0, dt, r.c->run_Ms.data(), 0);
         case SCH_LTS3: return r.lts3_step(dt, M);
         case SCH_LTS2: return r.lts2_step(dt, M);
         case SCH_SSPRK3: return r.rk3_step(dt);

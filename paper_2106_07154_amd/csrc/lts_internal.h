@@ -138,7 +138,8 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0,
                        const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                       const Aux<T>& aux2 = Aux<T>());
 // Lanes per cell in the cell kernel for a mesh whose largest cell has maxE edges.
 __host__ __device__ inline int padded_slots(int maxE) { return maxE <= 8 ? 8 : 16; }
 // Diagnostics partials per block (mass, energy, h_min, h_max, |u|max, nonfinite)

@@ -384,13 +384,16 @@ __device__ __forceinline__ void edge_body(const T* __restrict__ zs, int nE, int 
 }
 
 // Edge tendency U_e = Z_{c0}(e) + Z_{c1}(e) with its epilogue; blocks past the
-// edge range run the appended element-wise job.
+// edge range run the appended element-wise jobs (nba blocks of aux, then
+// aux2; the two touch disjoint elements).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_edge(const T* __restrict__ zs, int nE, int lo,
                                                  int hi, int nbe, Seg<T> s0, Seg<T> s1,
-                                                 Aux<T> aux, int* flag) {
+                                                 Aux<T> aux, int nba, Aux<T> aux2, int* flag) {
     if ((int)blockIdx.x >= nbe) {
-        run_aux(aux, (blockIdx.x - nbe) * kBlock + threadIdx.x);
+        const int b = blockIdx.x - nbe;
+        if (b < nba) run_aux(aux, b * kBlock + threadIdx.x);
+        else run_aux(aux2, (b - nba) * kBlock + threadIdx.x);
         return;
     }
     const int b = blockIdx.x, x = b & 7, k = b >> 3, qq = nbe >> 3, r = nbe & 7;
@@ -774,11 +777,13 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0, const Seg<T>& s1,
                        const Aux<T>& aux, int* flag, hipStream_t s, hipEvent_t ev0,
-                       hipEvent_t ev1) {
+                       hipEvent_t ev1, const Aux<T>& aux2) {
     const int nbe = hi > lo ? (int)nblocks(hi - lo) : 0;
     const int nba = aux.kind ? (int)nblocks((long)aux.nh + aux.nu) : 0;
-    if (nbe + nba == 0) return hipSuccess;
-    return launch(k_edge<T>, dim3(nbe + nba), s, ev0, ev1, zs, nE, lo, hi, nbe, s0, s1, aux, flag);
+    const int nba2 = aux2.kind ? (int)nblocks((long)aux2.nh + aux2.nu) : 0;
+    if (nbe + nba + nba2 == 0) return hipSuccess;
+    return launch(k_edge<T>, dim3(nbe + nba + nba2), s, ev0, ev1, zs, nE, lo, hi, nbe, s0, s1, aux,
+                  nba, aux2, flag);
 }
 
 // The wave-per-element map pays once few lanes of a wave go idle: measured
@@ -885,7 +890,8 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
                                        int, T, const Seg<T>&, const Seg<T>&, int*, hipStream_t,  \
                                        hipEvent_t, hipEvent_t);                                 \
     template hipError_t launch_edge<T>(const T*, int, int, int, const Seg<T>&, const Seg<T>&,    \
-                                       const Aux<T>&, int*, hipStream_t, hipEvent_t, hipEvent_t);\
+                                       const Aux<T>&, int*, hipStream_t, hipEvent_t, hipEvent_t, \
+                                       const Aux<T>&);                                          \
     template hipError_t launch_batch<T>(int, const Item<T>*, int, int, int, int, int,           \
                                         hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_diag<T>(const DevMesh<T>&, const T*, const T*, double, double*,   \

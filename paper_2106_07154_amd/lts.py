@@ -21,7 +21,8 @@ LTS_FP64, LTS_FP32 = 0, 1
 LTS_C, LTS_I2, LTS_I1, LTS_F = 0, 1, 2, 3
 KERNEL_CLASSES = ["vertex_pv", "cell_tendency", "edge_tendency"]
 
-EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_get_regions", "lts_init_state",
+EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_upload_mesh_levels",
+            "lts_get_level_regions", "lts_step_levels", "lts_plan_levels", "lts_get_regions", "lts_init_state",
             "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_step_scheme", "lts_eval_rhs",
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH):
         "lts_set_layers": ([P, ci], ci),
         "lts_upload_mesh": ([P, ctypes.POINTER(_Mesh), P, ci, ci, cd], ci),
         "lts_get_regions": ([P, P, P, P, P], ci),
+        "lts_upload_mesh_levels": ([P, ctypes.POINTER(_Mesh), ci, P, ci, ci, cd], ci),
+        "lts_get_level_regions": ([P, ci, P, P, P, P], ci),
+        "lts_step_levels": ([P, cd, P, ci], ci),
         "lts_init_state": ([P, P, P, cd], ci),
         "lts_init_state_device": ([P, P, P, cd], ci),
         "lts_step": ([P, cd, ci, ci], ci),
@@ -198,6 +202,28 @@ class LTSContext:
                                               int(n_if2), float(gravity)))
         self.mesh = mesh
 
+    def upload_mesh_levels(self, mesh, fine_masks, n_if1: int = 2, n_if2: int = 2,
+                           gravity: float = 9.81, use_positions: bool = True):
+        """Multi-level LTS3 mesh: fine_masks is a list of nested fine masks,
+        outermost first (Remark 3.1)."""
+        m, keep = _mesh_struct(mesh, use_positions)
+        fm = np.ascontiguousarray(np.stack([np.asarray(x, np.uint8) for x in fine_masks]))
+        self._check(self._lib.lts_upload_mesh_levels(self._h, ctypes.byref(m), fm.shape[0],
+                                                     _ptr(fm), int(n_if1), int(n_if2),
+                                                     float(gravity)))
+        self.mesh = mesh
+        self.n_fine_levels = fm.shape[0]
+
+    def level_regions(self, level: int):
+        m = self.mesh
+        cr = np.empty(m.nCells, np.int8)
+        er = np.empty(m.nEdges, np.int8)
+        cf = np.empty(m.nCells, np.uint8)
+        ef = np.empty(m.nEdges, np.uint8)
+        self._check(self._lib.lts_get_level_regions(self._h, int(level), _ptr(cr), _ptr(er),
+                                                    _ptr(cf), _ptr(ef)))
+        return cr, er, cf, ef
+
     def regions(self):
         m = self.mesh
         cr = np.empty(m.nCells, np.int8)
@@ -243,6 +269,12 @@ class LTSContext:
     # ---------------------------------------------------------------- stepping
     def step(self, dt_coarse: float, M: int, n_steps: int = 1):
         self._check(self._lib.lts_step(self._h, float(dt_coarse), int(M), int(n_steps)))
+
+    def step_levels(self, dt_coarse: float, Ms, n_steps: int = 1):
+        """Multi-level LTS3: Ms[l] is the step ratio of level l to level l+1."""
+        Ma = np.ascontiguousarray(Ms, np.int32)
+        self._check(self._lib.lts_step_levels(self._h, float(dt_coarse), _ptr(Ma),
+                                              int(n_steps)))
 
     def step_rk3(self, dt: float, n_steps: int = 1):
         self._check(self._lib.lts_step_rk3(self._h, float(dt), int(n_steps)))
@@ -351,6 +383,36 @@ def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = 
     out["passes"] = {name: dict(zip(["c_lo", "c_hi", "v_lo", "v_hi", "ct_lo", "ct_hi",
                                      "et_lo", "et_hi"], r[14 + 8 * k: 22 + 8 * k].tolist()))
                      for k, name in enumerate(PASS_NAMES)}
+    return out
+
+
+def plan_levels(mesh, fine_masks, n_if1: int = 2, n_if2: int = 2, use_positions: bool = True):
+    """Host-only lts_plan_levels: device ordering and per-level class starts and
+    pass ranges of a multi-level mesh (no GPU)."""
+    lib = load_library()
+    if not hasattr(lib, "_plan_levels_typed"):
+        P = ctypes.c_void_p
+        lib.lts_plan_levels.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_int, P, ctypes.c_int,
+                                        ctypes.c_int] + [P] * 4 + [ctypes.c_char_p, ctypes.c_int]
+        lib.lts_plan_levels.restype = ctypes.c_int
+        lib._plan_levels_typed = True
+    m, keep = _mesh_struct(mesh, use_positions)
+    fm = np.ascontiguousarray(np.stack([np.asarray(x, np.uint8) for x in fine_masks]))
+    nl = fm.shape[0]
+    out = dict(cell_order=np.empty(mesh.nCells, np.int32), edge_order=np.empty(mesh.nEdges, np.int32),
+               vertex_order=np.empty(mesh.nVertices, np.int32), ranges=np.empty(46 * nl, np.int32))
+    err = ctypes.create_string_buffer(512)
+    st = lib.lts_plan_levels(ctypes.byref(m), nl, _ptr(fm), int(n_if1), int(n_if2),
+                             *[_ptr(out[k]) for k in ("cell_order", "edge_order", "vertex_order",
+                                                      "ranges")], err, len(err))
+    if st != LTS_OK:
+        raise LTSError(st, err.value.decode())
+    r = out.pop("ranges").reshape(nl, 46)
+    keys = ["c_lo", "c_hi", "v_lo", "v_hi", "ct_lo", "ct_hi", "et_lo", "et_hi"]
+    out["levels"] = [dict(cell_class_start=r[l, :8].copy(), edge_class_start=r[l, 8:14].copy(),
+                          passes={name: dict(zip(keys, r[l, 14 + 8 * k: 22 + 8 * k].tolist()))
+                                  for k, name in enumerate(["step1", "step2", "step3", "step4"])})
+                     for l in range(nl)]
     return out
 
 

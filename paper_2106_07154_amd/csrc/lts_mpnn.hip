@@ -1,5 +1,6 @@
 // Message-passing surrogate kernels (gfx950): BF16 weights and activations,
-// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16).
+// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16 for the
+// layer products, v_mfma_f32_16x16x16_bf16 where a lane holds 4 values).
 //
 // Network over the cells of the fine and interface regions (the nodes),
 // neighbours = cells sharing an edge within that set:
@@ -38,6 +39,21 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 __device__ __forceinline__ f4 mfma(sh4 a, sh4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// gfx950's double-depth form: 8 BF16 per lane and operand, 32 products per
+// output element in one instruction.  Lane group g = l / 16 supplies k-slots
+// 8 g .. 8 g + 7 of the instruction in both operands, so any assignment of
+// reduction indices to those slots that is the same in A and B gives the
+// same sum.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf8 as_bf8(uint4 v) {
+    bf8 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+__device__ __forceinline__ f4 mfma32(uint4 a, uint4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
 }
 
 inline unsigned nblk(long n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -137,10 +153,7 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t* __restrict__ A, in
             if (wide) {
                 const uint4 wv = *reinterpret_cast<const uint4*>(wr + c * 16 * kWtStride + 8 * p);
 #pragma unroll
-                for (int q = 0; q < kGemmTiles; ++q) {
-                    acc[q][c] = mfma(bf4(wv.x, wv.y), bf4(av[q][p].x, av[q][p].y), acc[q][c]);
-                    acc[q][c] = mfma(bf4(wv.z, wv.w), bf4(av[q][p].z, av[q][p].w), acc[q][c]);
-                }
+                for (int q = 0; q < kGemmTiles; ++q) acc[q][c] = mfma32(wv, av[q][p], acc[q][c]);
             } else {
                 const uint2 wv = *reinterpret_cast<const uint2*>(wr + c * 16 * kWtStride + 4 * p);
 #pragma unroll

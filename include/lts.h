@@ -293,6 +293,39 @@ lts_status lts_ens_init_member(lts_ens *ens, int member, const double *h, const 
 lts_status lts_ens_build(lts_ens *ens, int autotune);
 /* Advance every member by n_steps coarse steps.  Asynchronous. */
 lts_status lts_ens_step(lts_ens *ens, int n_steps);
+/* Choose what one ensemble step does and drop the current build (call
+   lts_ens_build again; autotune = 0 keeps the previous tuning): scheme 0
+   (LTS3, the default) advances member j by one LTS3 coarse step of
+   dt_coarse[j] with its M; scheme 2 (global SSPRK3, Algorithm 2.1) advances
+   it over the same dt_coarse[j] in M_j SSPRK3 steps of dt_coarse[j]/M_j,
+   through the same batched work lists.  dt_coarse[n_members] (may be NULL:
+   keep each member's) replaces the coarse steps.  Member states are kept.
+   LTS_EINVAL for another scheme or a step <= 0. */
+lts_status lts_ens_set_scheme(lts_ens *ens, int scheme, const double *dt_coarse);
+/* Run each ensemble step as one persistent fused kernel (enable != 0) or as
+   the batched launches per (phase, kernel class, size class) (enable = 0, the
+   default), and drop the current build (call lts_ens_build again).  The
+   fused kernel is one cooperative launch of 256-thread blocks, as many as
+   fit on the device at once, that works through every phase of every
+   member's step, the vertex, cell and edge work of a phase separated by
+   grid-wide barriers on device-scope atomics; it is captured into the step's
+   hipGraph when the runtime accepts that, else launched directly.  Every
+   barrier wait is bounded by spin_limit polls (0: 2^22); one that runs out
+   makes every block leave the kernel, and lts_ens_step (which synchronises
+   in this mode) returns LTS_EDEVICE with the member states undefined until
+   they are re-initialised.  Results are those of the batched launches (same
+   arithmetic per element).  LTS_EINVAL for spin_limit < 0. */
+lts_status lts_ens_set_fused(lts_ens *ens, int enable, int spin_limit);
+/* Timing mode: advance every member by n_steps ensemble steps with each
+   batched launch stamped by HIP events (launches issued one after another on
+   the ensemble's stream, no graph), and return per kernel class (vertex,
+   cell, edge) the launch count, the summed kernel time in ms and the summed
+   algorithmic bytes (every array element a launch needs, read or written
+   once).  With the fused kernel every step is one launch, reported in the
+   cell entry (index 1) with the bytes of all three classes; the other two
+   entries are zero.  Synchronises.  LTS_ESTATE before lts_ens_build. */
+lts_status lts_ens_kernel_stats(lts_ens *ens, int n_steps, int64_t *launches, double *ms,
+                                double *bytes);
 lts_status lts_ens_get_member(lts_ens *ens, int member, double *h, double *u);
 lts_status lts_ens_diagnostics(lts_ens *ens, int member, lts_diag *out);
 /* Autotuner choices: tuned[(k*3+s)*2 + {0,1}] = block size, grid factor (grid =

@@ -52,8 +52,19 @@ struct lts_ens {
     double step_bytes[KC_N] = {0, 0, 0};  // algorithmic bytes of one ensemble step
     struct Launch {
         int sc, kclass, nitems, nvb, block, grid;
-        size_t off;  // first item in d_items
+        size_t off;    // first item in d_items
+        double bytes;  // algorithmic bytes of the launch
     };
+    int scheme = SCH_LTS3;  // LTS3, or SSPRK3 in M steps of dt/M per ensemble step
+    std::vector<hipEvent_t> evs;  // timing events, two per launch
+    // fused step: one cooperative launch per ensemble step
+    bool fused = false;
+    int spin_limit = 1 << 22;     // polls per bounded barrier wait
+    int fused_grid = 0, fused_nphase = 0;
+    bool fused_graph = false;     // the launch replays from the captured graph
+    void* d_phases = nullptr;
+    FusedBarrier* d_bar = nullptr;
+    double fused_bytes = 0.0;     // algorithmic bytes of one fused step
     std::vector<Launch> launches;
     void* d_items = nullptr;
     hipGraph_t graph = nullptr;
@@ -96,19 +107,23 @@ struct Builder {
             const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
             Run<T> r{c, dm, e->stream, false};
             r.rec = &recs[j];
-            lts_status st = r.lts3_step(e->dt[j], e->M[j]);
+            lts_status st = LTS_OK;
+            if (e->scheme == SCH_LTS3) st = r.lts3_step(e->dt[j], e->M[j]);
+            else
+                for (int k = 0; k < e->M[j] && !st; ++k) st = r.rk3_step(e->dt[j] / e->M[j]);
             if (st) return efail(e, st, "recording member " + std::to_string(j) + ": " + c->err);
             nphase = std::max(nphase, (int)recs[j].size());
         }
         return LTS_OK;
     }
 
-    // Work items of one launch; returns the number of virtual blocks.
+    // Work items of one launch (sc < 0: members of every class); returns the
+    // number of virtual blocks.
     int items(int t, int sc, int kclass, int block, std::vector<Item<T>>& out) const {
         out.clear();
         int first = 0;
         for (size_t j = 0; j < recs.size(); ++j) {
-            if (e->sclass[j] != sc || t >= (int)recs[j].size()) continue;
+            if ((sc >= 0 && e->sclass[j] != sc) || t >= (int)recs[j].size()) continue;
             lts_ctx* c = e->members[j];
             const PassRecord<T>& r = recs[j][t];
             const PassPlan& P = c->plan[r.kind];
@@ -130,7 +145,7 @@ struct Builder {
                 w.hi = P.c_hi;
                 w.s0 = r.cs0;
                 w.s1 = r.cs1;
-                n = (long)(P.c_hi - P.c_lo) * class_lanes(sc);
+                n = (long)(P.c_hi - P.c_lo) * class_lanes(e->sclass[j]);
             } else {
                 w.lo = P.et_lo;
                 w.hi = P.et_hi;
@@ -208,6 +223,58 @@ struct Builder {
         return LTS_OK;
     }
 
+    // Fused step: one item list per (phase, kernel class) over all members,
+    // one cooperative launch per step; captured into a graph when the runtime
+    // accepts the cooperative launch under capture, else launched directly.
+    lts_status finalize_fused() {
+        std::vector<Item<T>> all, it;
+        std::vector<FusedPhase> ph;
+        e->fused_bytes = 0.0;
+        for (int k = 0; k < KC_N; ++k) e->fused_bytes += e->step_bytes[k];
+        int max_nvb = 1;
+        for (int t = 0; t < nphase; ++t)
+            for (int k = 0; k < KC_N; ++k) {
+                const int nvb = items(t, -1, k, 256, it);
+                ph.push_back(FusedPhase{(int)all.size(), (int)it.size(), nvb});
+                all.insert(all.end(), it.begin(), it.end());
+                max_nvb = std::max(max_nvb, nvb);
+            }
+        const int per_cu = fused_blocks_per_cu<T>();
+        if (per_cu <= 0) return efail(e, LTS_EDEVICE, "fused step: occupancy query failed");
+        e->fused_grid = std::max(1, std::min(max_nvb, per_cu * e->n_cu));
+        e->fused_nphase = nphase;
+        EHIP(e, hipMalloc(&e->d_items, std::max<size_t>(all.size(), 1) * sizeof(Item<T>)));
+        if (!all.empty())
+            EHIP(e, hipMemcpy(e->d_items, all.data(), all.size() * sizeof(Item<T>),
+                              hipMemcpyHostToDevice));
+        EHIP(e, hipMalloc(&e->d_phases, std::max<size_t>(ph.size(), 1) * sizeof(FusedPhase)));
+        if (!ph.empty())
+            EHIP(e, hipMemcpy(e->d_phases, ph.data(), ph.size() * sizeof(FusedPhase),
+                              hipMemcpyHostToDevice));
+        if (!e->d_bar) {
+            EHIP(e, hipMalloc(&e->d_bar, sizeof(FusedBarrier)));
+            EHIP(e, hipMemset(e->d_bar, 0, sizeof(FusedBarrier)));
+        }
+        e->fused_graph = false;
+        if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            hipError_t err = launch_fused<T>(static_cast<const Item<T>*>(e->d_items),
+                                             static_cast<const FusedPhase*>(e->d_phases), nphase,
+                                             e->d_bar, e->spin_limit, e->fused_grid, e->stream);
+            hipGraph_t gr = nullptr;
+            hipError_t err2 = hipStreamEndCapture(e->stream, &gr);
+            if (err == hipSuccess && err2 == hipSuccess && gr &&
+                hipGraphInstantiate(&e->gexec, gr, nullptr, nullptr, 0) == hipSuccess) {
+                e->graph = gr;
+                e->fused_graph = true;
+            } else {
+                if (gr) (void)hipGraphDestroy(gr);
+                e->gexec = nullptr;
+                (void)hipGetLastError();
+            }
+        }
+        return LTS_OK;
+    }
+
     lts_status finalize() {
         std::vector<Item<T>> all, it;
         e->launches.clear();
@@ -219,6 +286,7 @@ struct Builder {
                 e->step_bytes[KC_CELL] += kernel_bytes<T>(P, KC_CELL, r.cs0, r.cs1, r.aux);
                 e->step_bytes[KC_EDGE] += kernel_bytes<T>(P, KC_EDGE, r.es0, r.es1, r.aux);
             }
+        if (e->fused) return finalize_fused();
         for (int sc = 0; sc < lts_ens::NCLS; ++sc)
             for (int t = 0; t < nphase; ++t)
                 for (int k = 0; k < KC_N; ++k) {
@@ -226,6 +294,14 @@ struct Builder {
                     const int nvb = items(t, sc, k, bs, it);
                     if (nvb == 0) continue;
                     lts_ens::Launch L;
+                    L.bytes = 0.0;
+                    for (size_t j = 0; j < recs.size(); ++j) {
+                        if (e->sclass[j] != sc || t >= (int)recs[j].size()) continue;
+                        const PassRecord<T>& r = recs[j][t];
+                        const PassPlan& P = e->members[j]->plan[r.kind];
+                        L.bytes += k == KC_EDGE ? kernel_bytes<T>(P, k, r.es0, r.es1, r.aux)
+                                                : kernel_bytes<T>(P, k, r.cs0, r.cs1, r.aux);
+                    }
                     L.sc = sc;
                     L.kclass = k;
                     L.nitems = (int)it.size();
@@ -274,7 +350,7 @@ lts_status build(lts_ens* e, int autotune) {
     Builder<T> b{e};
     lts_status st = b.record();
     if (st) return st;
-    if (autotune) {
+    if (autotune && !e->fused) {
         // tuning launches advance the members: keep their states and restore them
         std::vector<std::vector<double>> h(e->members.size()), u(e->members.size());
         for (size_t j = 0; j < e->members.size(); ++j) {
@@ -292,6 +368,94 @@ lts_status build(lts_ens* e, int autotune) {
         }
     }
     return b.finalize();
+}
+
+// Drop the recorded launches and their graph (the members keep their state).
+void unbuild(lts_ens* e) {
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->d_items) (void)hipFree(e->d_items);
+    if (e->d_phases) (void)hipFree(e->d_phases);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    e->d_items = nullptr;
+    e->d_phases = nullptr;
+    e->fused_graph = false;
+    e->launches.clear();
+    e->built = false;
+}
+
+// One fused ensemble step without the graph (event-stamped when ev0/ev1).
+template <typename T>
+hipError_t fused_launch(lts_ens* e, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    return launch_fused<T>(static_cast<const Item<T>*>(e->d_items),
+                           static_cast<const FusedPhase*>(e->d_phases), e->fused_nphase, e->d_bar,
+                           e->spin_limit, e->fused_grid, e->stream, ev0, ev1);
+}
+
+// After fused steps: wait for them and turn a barrier that gave up into
+// LTS_EDEVICE (the members' states are then undefined; re-initialise them).
+lts_status fused_check(lts_ens* e) {
+    EHIP(e, hipStreamSynchronize(e->stream));
+    FusedBarrier b;
+    EHIP(e, hipMemcpy(&b, e->d_bar, sizeof(b), hipMemcpyDeviceToHost));
+    if (b.err) {
+        EHIP(e, hipMemset(e->d_bar, 0, sizeof(FusedBarrier)));
+        for (lts_ctx* c : e->members) c->has_state = false;
+        return efail(e, LTS_EDEVICE,
+                     "fused step: a grid barrier wait ran out; member states are undefined");
+    }
+    return LTS_OK;
+}
+
+// n ensemble steps with every launch stamped by events, one after another on
+// the ensemble's stream (each size class's chain keeps its order).
+template <typename T>
+lts_status timed_steps(lts_ens* e, int n, int64_t* launches, double* ms, double* bytes) {
+    if (e->fused) {
+        while (e->evs.size() < 2) {
+            hipEvent_t ev;
+            EHIP(e, hipEventCreate(&ev));
+            e->evs.push_back(ev);
+        }
+        for (int i = 0; i < n; ++i) {
+            EHIP(e, fused_launch<T>(e, e->evs[0], e->evs[1]));
+            lts_status st = fused_check(e);
+            if (st) return st;
+            float t = 0.f;
+            EHIP(e, hipEventElapsedTime(&t, e->evs[0], e->evs[1]));
+            launches[KC_CELL] += 1;
+            ms[KC_CELL] += t;
+            bytes[KC_CELL] += e->fused_bytes;
+        }
+        return LTS_OK;
+    }
+    const size_t need = 2 * e->launches.size();
+    while (e->evs.size() < need) {
+        hipEvent_t ev;
+        EHIP(e, hipEventCreate(&ev));
+        e->evs.push_back(ev);
+    }
+    const Item<T>* base = static_cast<const Item<T>*>(e->d_items);
+    for (int i = 0; i < n; ++i) {
+        for (size_t q = 0; q < e->launches.size(); ++q) {
+            const auto& L = e->launches[q];
+            EHIP(e, launch_batch<T>(L.kclass, base + L.off, L.nitems, L.nvb, L.block, L.grid,
+                                    class_lanes(L.sc), e->stream, e->evs[2 * q],
+                                    e->evs[2 * q + 1]));
+        }
+        EHIP(e, hipStreamSynchronize(e->stream));
+        for (size_t q = 0; q < e->launches.size(); ++q) {
+            float t = 0.f;
+            EHIP(e, hipEventElapsedTime(&t, e->evs[2 * q], e->evs[2 * q + 1]));
+            const int k = e->launches[q].kclass;
+            launches[k] += 1;
+            ms[k] += t;
+            bytes[k] += e->launches[q].bytes;
+        }
+    }
+    return LTS_OK;
 }
 
 lts_status ens_ready(lts_ens* e) {
@@ -334,10 +498,9 @@ lts_status lts_ens_create(lts_ens** out, int device, lts_precision prec, void* h
 void lts_ens_destroy(lts_ens* e) {
     if (!e) return;
     (void)hipSetDevice(e->device);
-    if (e->stream) (void)hipStreamSynchronize(e->stream);
-    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    if (e->d_items) (void)hipFree(e->d_items);
+    unbuild(e);
+    if (e->d_bar) (void)hipFree(e->d_bar);
+    for (hipEvent_t ev : e->evs) (void)hipEventDestroy(ev);
     for (lts_ctx* c : e->members) lts_destroy(c);
     for (int k = 0; k < lts_ens::NCLS; ++k) {
         if (e->side[k]) (void)hipStreamDestroy(e->side[k]);
@@ -399,9 +562,19 @@ lts_status lts_ens_step(lts_ens* e, int n_steps) {
     if (s) return s;
     if (!e->built) return efail(e, LTS_ESTATE, "build the ensemble first");
     if (n_steps < 0) return efail(e, LTS_EINVAL, "n_steps < 0");
-    for (lts_ctx* c : e->members)
+    for (lts_ctx* c : e->members) {
         if (c->nonfinite) return efail(e, LTS_ENONFINITE, "a member is non-finite");
-    for (int i = 0; i < n_steps; ++i) EHIP(e, hipGraphLaunch(e->gexec, e->stream));
+        if (!c->has_state) return efail(e, LTS_ESTATE, "a member has no valid state");
+    }
+    if (e->fused) {
+        for (int i = 0; i < n_steps; ++i) {
+            if (e->fused_graph) EHIP(e, hipGraphLaunch(e->gexec, e->stream));
+            else if (e->prec == LTS_FP64) EHIP(e, fused_launch<double>(e));
+            else EHIP(e, fused_launch<float>(e));
+        }
+        if ((s = fused_check(e))) return s;
+    }
+    for (int i = 0; i < n_steps && !e->fused; ++i) EHIP(e, hipGraphLaunch(e->gexec, e->stream));
     for (size_t j = 0; j < e->members.size(); ++j) {
         e->members[j]->t += e->dt[j] * n_steps;
         e->members[j]->steps += n_steps;
@@ -424,6 +597,53 @@ lts_status lts_ens_diagnostics(lts_ens* e, int member, lts_diag* out) {
     if (member < 0 || member >= (int)e->members.size()) return efail(e, LTS_EINVAL, "no such member");
     s = lts_diagnostics(e->members[member], out);
     if (s) return efail(e, s, e->members[member]->err);
+    return LTS_OK;
+}
+
+lts_status lts_ens_set_scheme(lts_ens* e, int scheme, const double* dt_coarse) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (scheme != SCH_LTS3 && scheme != SCH_SSPRK3) return efail(e, LTS_EINVAL, "unsupported scheme");
+    if (dt_coarse)
+        for (size_t j = 0; j < e->members.size(); ++j)
+            if (!(dt_coarse[j] > 0)) return efail(e, LTS_EINVAL, "dt_coarse must be > 0");
+    unbuild(e);
+    e->scheme = scheme;
+    if (dt_coarse)
+        for (size_t j = 0; j < e->members.size(); ++j) e->dt[j] = dt_coarse[j];
+    return LTS_OK;
+}
+
+lts_status lts_ens_set_fused(lts_ens* e, int enable, int spin_limit) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (spin_limit < 0) return efail(e, LTS_EINVAL, "spin_limit < 0");
+    unbuild(e);
+    e->fused = enable != 0;
+    e->spin_limit = spin_limit > 0 ? spin_limit : (1 << 22);
+    return LTS_OK;
+}
+
+lts_status lts_ens_kernel_stats(lts_ens* e, int n_steps, int64_t* launches, double* ms,
+                                double* bytes) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (!e->built) return efail(e, LTS_ESTATE, "build the ensemble first");
+    if (n_steps < 0 || !launches || !ms || !bytes) return efail(e, LTS_EINVAL, "bad arguments");
+    for (int k = 0; k < KC_N; ++k) {
+        launches[k] = 0;
+        ms[k] = bytes[k] = 0.0;
+    }
+    for (lts_ctx* c : e->members)
+        if (c->nonfinite) return efail(e, LTS_ENONFINITE, "a member is non-finite");
+    s = e->prec == LTS_FP64 ? timed_steps<double>(e, n_steps, launches, ms, bytes)
+                            : timed_steps<float>(e, n_steps, launches, ms, bytes);
+    if (s) return s;
+    for (size_t j = 0; j < e->members.size(); ++j) {
+        e->members[j]->t += e->dt[j] * n_steps;
+        e->members[j]->steps += n_steps;
+    }
+    e->steps += n_steps;
     return LTS_OK;
 }
 

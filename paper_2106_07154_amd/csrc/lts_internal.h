@@ -122,6 +122,27 @@ hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, i
                         int grid, int G, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 
+// Fused ensemble step (one cooperative launch of 256-thread blocks): phase t,
+// kernel class k works on items [off, off + nitems) of the item array with
+// nvb virtual blocks; the classes are separated by grid barriers.
+struct FusedPhase {
+    int off, nitems, nvb;
+};
+// Grid-barrier state in device memory: arrivals, generation, error word
+// (non-zero once a bounded wait ran out; every block then leaves the kernel).
+// count must be 0 before a launch; a completed launch leaves it 0.
+struct FusedBarrier {
+    unsigned count, gen;
+    int err;
+    int pad;
+};
+template <typename T>
+int fused_blocks_per_cu();  // co-resident 256-thread blocks per CU (0 on error)
+template <typename T>
+hipError_t launch_fused(const Item<T>* items, const FusedPhase* phases, int nphase,
+                        FusedBarrier* bar, int limit, int grid, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 // Launchers (lts_kernels.hip).  All enqueue on `s` and return the launch
 // error.  With non-null ev0/ev1 the launch goes through hipExtLaunchKernelGGL,
 // which stamps the kernel's own start and end into the two events (timing mode;

@@ -457,6 +457,91 @@ __global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused ensemble step: one persistent cooperative launch runs every phase of
+// every member's coarse step, the kernel classes of a phase (vertex, cell,
+// edge) separated by grid-wide barriers.  Work lists as for the batched
+// kernels above, one per (phase, class), members of every size and lane
+// count together.
+
+// Grid barrier on device-scope vector atomics.  Each block's thread 0 reads
+// the generation, releases the block's writes (device fence), arrives on the
+// counter; the last arrival resets the counter and advances the generation,
+// the others wait for that advance.  Every wait is bounded: after `limit`
+// polls the block records the failure in bar->err and the barrier reports
+// false; every later barrier of the launch then returns false at once, so
+// all blocks leave the kernel.
+__device__ __forceinline__ bool grid_barrier(FusedBarrier* bar, unsigned nblocks, int limit) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = __hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        if (good) {
+            const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (arrived == nblocks) {
+                __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                int polls = 0;
+                while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    if (++polls > limit) {
+                        __hip_atomic_fetch_or(&bar->err, 1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        good = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __threadfence();
+        }
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kf_step(const Item<T>* __restrict__ items,
+                                               const FusedPhase* __restrict__ phases, int nphase,
+                                               FusedBarrier* bar, int limit) {
+    const unsigned nb = gridDim.x;
+    for (int t = 0; t < nphase; ++t) {
+        for (int k = 0; k < KC_N; ++k) {
+            const FusedPhase P = phases[t * KC_N + k];
+            const Item<T>* it = items + P.off;
+            for (int vb = blockIdx.x; vb < P.nvb; vb += (int)nb) {
+                const Item<T>& w = it[find_item(it, P.nitems, vb)];
+                const int j = vb - w.first;
+                const int lt = j * (int)blockDim.x + threadIdx.x;
+                if (k == KC_VERTEX) {
+                    const int v = w.lo + lt;
+                    if (v < w.hi) vertex_body<T, perturbation_form<T>()>(w.m, w.h, w.u, w.q, v);
+                } else if (k == KC_CELL) {
+                    if (padded_slots(w.m.maxE) == 8)
+                        cell_body<T, 8, perturbation_form<T>(), false>(w.m, w.h, w.u, w.q, w.zs, lt,
+                                                                       w.lo, w.hi, w.g, w.s0, w.s1,
+                                                                       w.flag);
+                    else
+                        cell_body<T, 16, perturbation_form<T>(), false>(w.m, w.h, w.u, w.q, w.zs,
+                                                                        lt, w.lo, w.hi, w.g, w.s0,
+                                                                        w.s1, w.flag);
+                } else if (j < w.nblk) {
+                    const int e = w.lo + lt;
+                    if (e < w.hi) edge_body(w.zs, w.m.nE, e, w.s0, w.s1, w.flag);
+                } else {
+                    run_aux(w.aux, (j - w.nblk) * (int)blockDim.x + threadIdx.x);
+                }
+            }
+            if (!grid_barrier(bar, nb, limit)) return;
+        }
+    }
+}
+
 // Diagnostics: block partials [mass, energy, -h_min, h_max, |u|max, nonfinite]
 // as doubles, in a fixed tree order (deterministic).
 template <typename T>
@@ -867,6 +952,29 @@ hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, i
 }
 
 template <typename T>
+int fused_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kf_step<T>),
+                                                     256, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+template <typename T>
+hipError_t launch_fused(const Item<T>* items, const FusedPhase* phases, int nphase,
+                        FusedBarrier* bar, int limit, int grid, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+    void* args[] = {(void*)&items, (void*)&phases, (void*)&nphase, (void*)&bar, (void*)&limit};
+    hipError_t e = hipSuccess;
+    if (ev0) e = hipEventRecord(ev0, s);
+    if (e == hipSuccess)
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kf_step<T>), dim3(grid),
+                                       dim3(256), args, 0, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    return e;
+}
+
+template <typename T>
 hipError_t launch_diag(const DevMesh<T>& m, const T* h, const T* u, double g, double* part,
                        int nblk_cells, int nblk_edges, double* out, hipStream_t s, int L) {
     hipLaunchKernelGGL(k_diag_part<T>, dim3(nblk_cells + nblk_edges), dim3(kBlock), 0, s, m, h,
@@ -894,6 +1002,9 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
                                        const Aux<T>&);                                          \
     template hipError_t launch_batch<T>(int, const Item<T>*, int, int, int, int, int,           \
                                         hipStream_t, hipEvent_t, hipEvent_t);                  \
+    template int fused_blocks_per_cu<T>();                                                      \
+    template hipError_t launch_fused<T>(const Item<T>*, const FusedPhase*, int, FusedBarrier*,  \
+                                        int, int, hipStream_t, hipEvent_t, hipEvent_t);         \
     template hipError_t launch_diag<T>(const DevMesh<T>&, const T*, const T*, double, double*,   \
                                        int, int, double*, hipStream_t, int);                     \
     template hipError_t launch_vertex_l<T>(const DevMesh<T>&, const T*, const T*, T*, int, int,  \

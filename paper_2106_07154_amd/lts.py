@@ -27,7 +27,9 @@ EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_upload_mesh_
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
             "lts_ens_create", "lts_ens_add_member", "lts_ens_init_member", "lts_ens_build",
-            "lts_ens_step", "lts_ens_get_member", "lts_ens_diagnostics", "lts_ens_info",
+            "lts_ens_step", "lts_ens_set_scheme", "lts_ens_set_fused", "lts_ens_kernel_stats",
+            "lts_ens_get_member",
+            "lts_ens_diagnostics", "lts_ens_info",
             "lts_ens_last_error", "lts_ens_destroy",
             "lts_sur_create", "lts_sur_info", "lts_sur_node_map", "lts_sur_record",
             "lts_sur_normalize", "lts_sur_set_norm", "lts_sur_get_norm", "lts_sur_get_params",
@@ -120,6 +122,9 @@ def load_library(path: str = LIB_PATH):
         "lts_ens_init_member": ([P, ci, P, P], ci),
         "lts_ens_build": ([P, ci], ci),
         "lts_ens_step": ([P, ci], ci),
+        "lts_ens_set_scheme": ([P, ci, P], ci),
+        "lts_ens_set_fused": ([P, ci, ci], ci),
+        "lts_ens_kernel_stats": ([P, ci, P, P, P], ci),
         "lts_ens_get_member": ([P, ci, P, P], ci),
         "lts_ens_diagnostics": ([P, ci, ctypes.POINTER(_Diag)], ci),
         "lts_ens_info": ([P, P, P, P, P, P], ci),
@@ -481,6 +486,30 @@ class Ensemble:
         self._check(self._lib.lts_ens_diagnostics(self._h, int(j), ctypes.byref(d)))
         return Diag(d.t, d.mass, d.energy, d.h_min, d.h_max, d.u_absmax, d.n_nonfinite, d.steps,
                     d.gate_fallbacks)
+
+    def set_scheme(self, scheme: str, dt_coarse=None):
+        """'lts3' or 'ssprk3' (M_j SSPRK3 steps of dt_j/M_j per ensemble step);
+        optional new coarse steps per member.  Rebuild afterwards."""
+        code = {"lts3": 0, "ssprk3": 2}[scheme]
+        d = None if dt_coarse is None else np.ascontiguousarray(dt_coarse, np.float64)
+        self._check(self._lib.lts_ens_set_scheme(self._h, code, None if d is None else _ptr(d)))
+
+    def set_fused(self, enable: bool = True, spin_limit: int = 0):
+        """One persistent fused kernel per ensemble step (rebuild afterwards);
+        spin_limit bounds every grid-barrier wait (0: the default)."""
+        self._check(self._lib.lts_ens_set_fused(self._h, int(bool(enable)), int(spin_limit)))
+
+    def kernel_stats(self, n_steps: int):
+        """Event-stamped per-class statistics of n_steps ensemble steps (the
+        members advance)."""
+        n = np.zeros(3, np.int64)
+        ms = np.zeros(3)
+        by = np.zeros(3)
+        self._check(self._lib.lts_ens_kernel_stats(self._h, int(n_steps), _ptr(n), _ptr(ms),
+                                                   _ptr(by)))
+        names = ["vertex_pv", "cell_tendency", "edge_tendency"]
+        return {names[k]: {"launches": int(n[k]), "ms": float(ms[k]), "bytes": float(by[k])}
+                for k in range(3)}
 
     def info(self):
         tuned = np.zeros(18, np.int32)

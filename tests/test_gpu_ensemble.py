@@ -136,3 +136,125 @@ def test_config4_members_match_oracle(config4_members, prec):
         d = ens.diagnostics(j)
         assert d.steps == 2 and d.n_nonfinite == 0
     ens.close()
+
+
+def test_batched_ssprk3_and_kernel_stats(members):
+    """The ensemble's SSPRK3 mode (M_j steps of dt_j / M_j per ensemble step,
+    the same batched work lists) equals each member's own SSPRK3 in FP64 to
+    1e-14 and the FP64 oracle to 1e-12 (h) / 1e-11 (u); the event-stamped
+    timing mode advances the members like lts_ens_step and reports every
+    launch with its algorithmic bytes."""
+    say("ensemble ssprk3 + kernel stats")
+    ens = lts.Ensemble(0, "fp64")
+    for m, fm, h, u, dt, M in members:
+        ens.add_member(m, fm, dt, M)
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        ens.init_member(j, h, u)
+    dts = np.array([dt for *_, dt, M in members]) * 0.75
+    ens.set_scheme("ssprk3", dts)
+    ens.build(autotune=False)
+    ens.step(2)
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        gh, gu = ens.get_member(j)
+        c = lts.LTSContext(0, "fp64")
+        c.upload_mesh(m, fm, 2, 2)
+        c.init_state(h, u)
+        c.step_rk3(dts[j] / M, 2 * M)
+        rh, ru = c.get_state()
+        c.close()
+        assert rel_l2(gh, rh) <= 1e-14 and rel_l2(gu, ru) <= 1e-13, j
+        if m.nCells <= 20000:
+            oh, ou = Oracle(m).ssprk(h, u, dts[j] / M, n=2 * M)
+            assert rel_l2(gh, oh) < 1e-12 and rel_l2(gu, ou) < 1e-11, j
+        assert ens.diagnostics(j).steps == 2
+    # timing mode: same result as graph replay, every launch counted
+    info = ens.info()
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        ens.init_member(j, h, u)
+    st = ens.kernel_stats(2)
+    assert sum(v["launches"] for v in st.values()) == 2 * info["launches_per_step"]
+    for k, v in st.items():
+        assert v["launches"] > 0 and v["ms"] > 0, k
+        assert abs(v["bytes"] - 2 * info["step_bytes"][k]) <= 1e-6 * v["bytes"], k
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        gh, gu = ens.get_member(j)
+        c = lts.LTSContext(0, "fp64")
+        c.upload_mesh(m, fm, 2, 2)
+        c.init_state(h, u)
+        c.step_rk3(dts[j] / M, 2 * M)
+        rh, ru = c.get_state()
+        c.close()
+        assert np.array_equal(gh, rh) or rel_l2(gh, rh) <= 1e-14, j
+    # back to LTS3 at the original steps, keeping the tuning
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        ens.init_member(j, h, u)
+    ens.set_scheme("lts3", np.array([dt for *_, dt, M in members]))
+    ens.build(autotune=False)
+    ens.step(1)
+    m, fm, h, u, dt, M = members[0]
+    gh, gu = ens.get_member(0)
+    o = Oracle(m)
+    rh, ru = o.lts(h, u, dt, M, o.regions(fm, 2, 2), n=1)
+    assert rel_l2(gh, rh) < 1e-12 and rel_l2(gu, ru) < 1e-11
+    ens.close()
+
+
+def _ensemble(members, prec, fused, spin_limit=0):
+    ens = lts.Ensemble(0, prec)
+    for m, fm, h, u, dt, M in members:
+        ens.add_member(m, fm, dt, M)
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        ens.init_member(j, h, u)
+    if fused:
+        ens.set_fused(True, spin_limit)
+    ens.build(autotune=False)
+    return ens
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_step_matches_batched_launches(members, prec):
+    """One persistent fused kernel per ensemble step (grid barriers between
+    the vertex, cell and edge work of each phase) computes every element with
+    the arithmetic of the batched launches: bitwise equal members, and each
+    step is one launch."""
+    say("fused ensemble", prec)
+    a = _ensemble(members, prec, True)
+    b = _ensemble(members, prec, False)
+    a.step(3)
+    b.step(3)
+    for j in range(len(members)):
+        ha, ua = a.get_member(j)
+        hb, ub = b.get_member(j)
+        assert np.array_equal(ha, hb) and np.array_equal(ua, ub), j
+        assert a.diagnostics(j).steps == 3
+    st = a.kernel_stats(2)
+    assert st["cell_tendency"]["launches"] == 2 and st["vertex_pv"]["launches"] == 0
+    assert st["cell_tendency"]["ms"] > 0
+    a.close()
+    b.close()
+
+
+def test_fused_barrier_that_gives_up_is_an_error(members):
+    """A grid-barrier wait bounded to one poll runs out (forced from the
+    host): every block leaves the kernel, the step reports LTS_EDEVICE, and
+    after re-initialisation the default bound steps normally again."""
+    say("fused ensemble forced barrier timeout")
+    a = _ensemble(members, "fp64", True, spin_limit=1)
+    with pytest.raises(lts.LTSError) as ei:
+        a.step(1)
+    assert ei.value.status == lts.LTS_EDEVICE
+    with pytest.raises(lts.LTSError):
+        a.step(1)                      # states undefined until re-initialised
+    a.set_fused(True, 0)
+    for j, (m, fm, h, u, dt, M) in enumerate(members):
+        a.init_member(j, h, u)
+    a.build(autotune=False)
+    a.step(2)
+    b = _ensemble(members, "fp64", False)
+    b.step(2)
+    for j in range(len(members)):
+        ha, ua = a.get_member(j)
+        hb, ub = b.get_member(j)
+        assert np.array_equal(ha, hb) and np.array_equal(ua, ub), j
+    a.close()
+    b.close()

@@ -389,6 +389,9 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     dm->maxE = c->maxE;
     lts_status s;
     if ((s = upload_vec<int32_t>(c, &dm->nEoC, nEoC))) return s;
+    dm->nwide = (int)c->wide.size();
+    dm->wide = nullptr;
+    if (dm->nwide && (s = upload_vec<int32_t>(c, &dm->wide, c->wide))) return s;
     {
         const int32_t* p = nullptr;
         if ((s = upload_vec<int32_t>(c, &p, cso))) return s;
@@ -511,6 +514,8 @@ PassPlan plan_cover(const lts_ctx* c, const lts_mesh* m, int ct_lo, int ct_hi, i
     if (hi <= lo) { lo = hi = 0; }
     P.c_lo = lo;
     P.c_hi = hi;
+    P.w_lo = (int)(std::lower_bound(c->wide.begin(), c->wide.end(), lo) - c->wide.begin());
+    P.w_hi = (int)(std::lower_bound(c->wide.begin(), c->wide.end(), hi) - c->wide.begin());
     int vlo = c->nV, vhi = 0;
     std::vector<char> useu(nE, 0), useh(nC, 0), useq(c->nV, 0);
     long slots = 0;
@@ -962,6 +967,9 @@ lts_status plan_mesh(lts_ctx* c, const lts_mesh* m, const uint8_t* fine, int n1,
     });
     c->vinv.assign(nV, 0);
     for (int nv = 0; nv < nV; ++nv) c->vinv[c->vperm[nv]] = nv;
+    c->wide.clear();
+    for (int ni = 0; ni < nC; ++ni)
+        if (m->n_edges_on_cell[c->cperm[ni]] > 8) c->wide.push_back(ni);
     make_plans(c, m);
     return LTS_OK;
 }

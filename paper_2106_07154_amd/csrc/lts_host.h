@@ -18,6 +18,7 @@ enum PassKind { P_FULL = 0, P_STEP1, P_STEP2, P_STEP3, P_STEP4, P_N };
 struct PassPlan {
     int c_lo = 0, c_hi = 0;    // cell kernel range (targets plus cells of target edges)
     int v_lo = 0, v_hi = 0;    // vertex kernel range
+    int w_lo = 0, w_hi = 0;    // cells of the cell range with more than 8 edges (wide list)
     int ct_lo = 0, ct_hi = 0;  // target cells
     int et_lo = 0, et_hi = 0;  // target edges
     // algorithmic bytes of the gathers, per element type (counts of unique
@@ -61,6 +62,7 @@ struct lts_ctx {
     int L = 1;  // independent layers; per-element device arrays are [element][L]
     double g = 9.81;
     std::vector<int32_t> cperm, cinv, eperm, einv, vperm, vinv;  // perm: new->old, inv: old->new
+    std::vector<int32_t> wide;  // device positions of cells with more than 8 edges
     std::vector<int8_t> creg, ereg;                              // caller numbering
     std::vector<uint8_t> cfbar, efbar;
     int cb[8] = {0};  // cell class starts: Fint F2 F1 I1 I2 C1 Crest end
@@ -239,8 +241,8 @@ struct Run {
         HIPCHK(c, launch_vertex<T>(dm, h, u, q, P.v_lo, P.v_hi, s, e0, e1));
         done(KC_VERTEX, e0, e1, kernel_bytes<T>(P, KC_VERTEX, cs0, cs1, aux));
         if ((st = events(&e0, &e1))) return st;
-        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, (T)c->g, cs0, cs1, c->flag,
-                                 s, e0, e1));
+        HIPCHK(c, launch_cell<T>(dm, h, u, q, zs, P.c_lo, P.c_hi, P.w_lo, P.w_hi, (T)c->g, cs0,
+                                 cs1, c->flag, s, e0, e1));
         done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux));
         // edge tendency (+ appended element-wise job)
         if ((st = events(&e0, &e1))) return st;

@@ -29,6 +29,8 @@ struct DevMesh {
     int nC, nE, nV, maxE;  // maxE: largest n_i of the mesh
     const int32_t* nEoC;   // [nC] n_i
     const int2* cso;       // [nC] {first slot-table entry of cell i, n_i}
+    const int32_t* wide;   // [nwide] cells with more than 8 edges, ascending
+    int nwide;
     const int32_t* eoc;    // [slots] edge of slot j (ccw)
     const int32_t* coc;    // [slots] cell across edge j
     const int32_t* voc;    // [slots] vertex between edge j and j+1
@@ -151,10 +153,13 @@ template <typename T>
 hipError_t launch_vertex(const DevMesh<T>& m, const T* h, const T* u, T* q, int v_lo,
                          int v_hi, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
+// Cell kernel over [c_lo, c_hi): 8 lanes per cell; cells with more than 8
+// edges (entries [w_lo, w_hi) of m.wide, all inside the range) are taken by
+// 16-lane blocks appended to the same launch.
 template <typename T>
 hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs,
-                       int c_lo, int c_hi, T g, const Seg<T>& s0, const Seg<T>& s1,
-                       int* flag, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       int c_lo, int c_hi, int w_lo, int w_hi, T g, const Seg<T>& s0,
+                       const Seg<T>& s1, int* flag, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_edge(const T* zs, int nE, int lo, int hi, const Seg<T>& s0,

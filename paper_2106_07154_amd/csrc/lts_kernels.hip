@@ -269,7 +269,7 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     c.o = (size_t)so.x + min(lane, so.y - 1);
     c.i = i;
     c.lane = lane;
-    c.live = live;
+    c.live = live && so.y <= G;  // wider cells: the 16-lane list kernel
     c.e = m.eoc[c.o];
     const int nb = m.coc[c.o];
     c.nl = lane < so.y ? m.nl[c.o] : T(0);
@@ -343,14 +343,39 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     cell_math<T, G, PRE>(m, c, q[m.voc[c.o]], zs, g, s0, s1, flag);
 }
 
-template <typename T, int G, int HR>
+// Cells with more than 8 edges are not handled by their 8-lane groups (their
+// lanes are dead, see cell_loads): nbw blocks appended to the launch take
+// them from the mesh's list of such cells (entries [w_lo, w_hi)), 16 lanes
+// each, so a mesh with a few wide cells keeps 8 lanes everywhere else and
+// needs no extra launch.  The appended branch costs scalar registers (106
+// against 74, one wave per SIMD less), so it is compiled in (WIDE) only for
+// meshes that have such cells.
+template <typename T, int HR, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
-                                                 int* flag) {
-    cell_body<T, G, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
-                              s0, s1, flag);
+                                                 int* flag, int nbc, int w_lo, int w_hi) {
+    if (!WIDE) {
+        cell_body<T, 8, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi,
+                                  g, s0, s1, flag);
+        return;
+    }
+    const int b = blockIdx.x;
+    if (b >= nbc) {
+        const int t = (b - nbc) * kBlock + threadIdx.x;
+        const int p = w_lo + t / 16;
+        const bool live = p < w_hi;
+        const int i = m.wide[live ? p : w_hi - 1];
+        const CellLane<T> c = cell_loads<T, 16, HR, true>(m, h, u, i, t & 15, live, s0, s1);
+        cell_math<T, 16, true>(m, c, q[m.voc[c.o]], zs, g, s0, s1, flag);
+        return;
+    }
+    // blocks spread over the 8 XCDs as in xcd_block, over the nbc cell blocks
+    const int x = b & 7, k = b >> 3, qq = nbc >> 3, r = nbc & 7;
+    const int lb = x < r ? x * (qq + 1) + k : r * (qq + 1) + (x - r) * qq + k;
+    cell_body<T, 8, HR, true>(m, h, u, q, zs, lb * kBlock + threadIdx.x, c_lo, c_hi, g, s0, s1,
+                              flag);
 }
 
 template <typename T>
@@ -847,15 +872,17 @@ hipError_t launch_vertex(const DevMesh<T>& m, const T* h, const T* u, T* q, int 
 
 template <typename T>
 hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, T* zs, int c_lo,
-                       int c_hi, T g, const Seg<T>& s0, const Seg<T>& s1, int* flag,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                       int c_hi, int w_lo, int w_hi, T g, const Seg<T>& s0, const Seg<T>& s1,
+                       int* flag, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (c_hi <= c_lo) return hipSuccess;
-    const int G = padded_slots(m.maxE);
-    const dim3 grid(nblocks((long)(c_hi - c_lo) * G));
-#define LTS_CELL(GG, HR) \
-    launch(k_cell<T, GG, HR>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag)
-    if (m.href) return G == 8 ? LTS_CELL(8, 1) : LTS_CELL(16, 1);
-    return G == 8 ? LTS_CELL(8, 0) : LTS_CELL(16, 0);
+    const int nbc = (int)nblocks((long)(c_hi - c_lo) * 8);
+    const int nbw = w_hi > w_lo ? (int)nblocks((long)(w_hi - w_lo) * 16) : 0;
+    const dim3 grid(nbc + nbw);
+#define LTS_CELL(HR, W) \
+    launch(k_cell<T, HR, W>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag, nbc, \
+           w_lo, w_hi)
+    if (m.href) return nbw ? LTS_CELL(1, true) : LTS_CELL(1, false);
+    return nbw ? LTS_CELL(0, true) : LTS_CELL(0, false);
 #undef LTS_CELL
 }
 
@@ -995,8 +1022,8 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
     template hipError_t launch_vertex<T>(const DevMesh<T>&, const T*, const T*, T*, int, int,    \
                                          hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_cell<T>(const DevMesh<T>&, const T*, const T*, const T*, T*, int, \
-                                       int, T, const Seg<T>&, const Seg<T>&, int*, hipStream_t,  \
-                                       hipEvent_t, hipEvent_t);                                 \
+                                       int, int, int, T, const Seg<T>&, const Seg<T>&, int*,     \
+                                       hipStream_t, hipEvent_t, hipEvent_t);                    \
     template hipError_t launch_edge<T>(const T*, int, int, int, const Seg<T>&, const Seg<T>&,    \
                                        const Aux<T>&, int*, hipStream_t, hipEvent_t, hipEvent_t, \
                                        const Aux<T>&);                                          \

@@ -439,6 +439,46 @@ def test_training_reduces_loss_and_gate_accepts(igw):
     assert d.n_nonfinite == 0 and d.steps == 44
 
 
+def test_trained_network_gains_over_forward_euler(igw):
+    """What training buys.  All-zero parameters make the network output zero,
+    so the prediction on F is the forward-Euler step x_n + dt R(x_n), the
+    method without a learned correction.  From three held-out states (the
+    40 recorded LTS3 steps are followed by plain LTS3 steps never trained
+    on), one surrogate coarse step with the trained network and one with the
+    zero network are each compared with one plain LTS3 step from the same
+    state: the trained network's error in the step's height and velocity
+    increments, and its gate residual, are smaller on every state."""
+    w = igw
+    say("surrogate gain over forward Euler", w.name)
+    c = _ctx(w)
+    sur = lts.Surrogate(c, seed=5, max_samples=40)
+    sur.record(w.dt_coarse, w.M, 40)
+    sur.normalize()
+    sur.train(np.random.default_rng(0).integers(0, 32, 600), lr=2e-3)
+    trained = sur.get_params()
+    zero = np.zeros(sur.n_params, np.float32)
+    rows = []
+    for k in range(3):
+        c.step(w.dt_coarse, w.M, 1)            # a state no sample was taken from
+        h0, u0 = c.get_state()
+        c.step(w.dt_coarse, w.M, 1)
+        hl, ul = c.get_state()
+        got = {}
+        for name, p in (("trained", trained), ("zero", zero)):
+            sur.set_params(p)
+            c.init_state(h0, u0)
+            acc, res = sur.step(w.dt_coarse, w.M, 1, tau=1e30)
+            assert acc == 1
+            h, u = c.get_state()
+            got[name] = (rel_l2(h - h0, hl - h0), rel_l2(u - u0, ul - u0), float(res[0]))
+        rows.append(got)
+        say("state", k, "trained (eh, eu, r)", got["trained"], "zero", got["zero"])
+        c.init_state(hl, ul)
+    for got in rows:
+        for j in range(3):
+            assert got["trained"][j] < got["zero"][j], (j, got)
+
+
 def test_gate_backoff_schedule(igw):
     w = igw
     say("surrogate back-off")

@@ -400,7 +400,7 @@ lts_status fused_check(lts_ens* e) {
     EHIP(e, hipStreamSynchronize(e->stream));
     FusedBarrier b;
     EHIP(e, hipMemcpy(&b, e->d_bar, sizeof(b), hipMemcpyDeviceToHost));
-    if (b.err) {
+    if (fused_barrier_error(b)) {
         EHIP(e, hipMemset(e->d_bar, 0, sizeof(FusedBarrier)));
         for (lts_ctx* c : e->members) c->has_state = false;
         return efail(e, LTS_EDEVICE,

@@ -130,14 +130,19 @@ hipError_t launch_batch(int kclass, const Item<T>* items, int nitems, int nvb, i
 struct FusedPhase {
     int off, nitems, nvb;
 };
-// Grid-barrier state in device memory: arrivals, generation, error word
-// (non-zero once a bounded wait ran out; every block then leaves the kernel).
-// count must be 0 before a launch; a completed launch leaves it 0.
+// Grid-barrier workspace in device memory, 128-byte lines of kBarLine words:
+// line 0 arrivals of the XCD leaders, 1 generation, 2 error word (non-zero
+// once a bounded wait ran out; every block then leaves the kernel), 3 + x
+// the number of the launch's blocks running on XCD x (counted at kernel
+// start), 19 + x arrivals on XCD x, 35 + x release flag of XCD x (x < 16).
+// All zero before the first launch; a completed launch leaves lines 0, 2,
+// 3..18 and 19..34 zero again.
+constexpr int kBarLine = 32;
+constexpr int kBarXcds = 16;
 struct FusedBarrier {
-    unsigned count, gen;
-    int err;
-    int pad;
+    unsigned w[(3 + 3 * kBarXcds) * kBarLine];
 };
+inline unsigned fused_barrier_error(const FusedBarrier& b) { return b.w[2 * kBarLine]; }
 template <typename T>
 int fused_blocks_per_cu();  // co-resident 256-thread blocks per CU (0 on error)
 template <typename T>

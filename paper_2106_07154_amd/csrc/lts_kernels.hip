@@ -489,40 +489,124 @@ __global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items
 // kernels above, one per (phase, class), members of every size and lane
 // count together.
 
-// Grid barrier on device-scope vector atomics.  Each block's thread 0 reads
-// the generation, releases the block's writes (device fence), arrives on the
-// counter; the last arrival resets the counter and advances the generation,
-// the others wait for that advance.  Every wait is bounded: after `limit`
-// polls the block records the failure in bar->err and the barrier reports
-// false; every later barrier of the launch then returns false at once, so
-// all blocks leave the kernel.
-__device__ __forceinline__ bool grid_barrier(FusedBarrier* bar, unsigned nblocks, int limit) {
+// Grid barrier.  The 8 XCDs each have their own L2, not coherent with the
+// others, so a block's writes become visible to other XCDs only after an L2
+// write-back and reads see other XCDs' writes only after an L2 invalidate
+// (the agent-scope release and acquire).  Done by every block, the write-back
+// serialises on each XCD's L2 and dominates the barrier.  Here one block per
+// XCD writes back for all: every block waits for its own stores to reach the
+// L2 (s_waitcnt) and arrives on its XCD's counter; the XCD's last arrival
+// (its leader) writes the L2 back, arrives on the top counter, waits for the
+// generation to advance, invalidates and raises the XCD's flag; the other
+// blocks wait for the flag and invalidate (their CU's L1 needs it; the
+// invalidate cannot be narrowed to the L1).  Which XCD a block runs on is read
+// from the hardware (XCC_ID), and the blocks per XCD are counted at kernel
+// start, so no placement is assumed.  Every wait is bounded: after `limit`
+// polls the block records the failure in the error word and the barrier
+// reports false; every later barrier of the launch then returns false at
+// once, so all blocks leave the kernel.
+__device__ __forceinline__ unsigned* bar_word(FusedBarrier* bar, int line) {
+    return bar->w + line * kBarLine;
+}
+__device__ __forceinline__ unsigned ld_agent(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned add_agent(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The value v has arrived (its load or atomic has been performed) before any
+// later memory operation issues: a wait on v plus a compiler barrier.  Used
+// where two relaxed operations on different words must take effect in order.
+__device__ __forceinline__ void arrived(unsigned v) { asm volatile("" ::"v"(v) : "memory"); }
+// Poll *p until it differs from old; false (and the error word set) after
+// `limit` polls.
+__device__ __forceinline__ bool bar_wait(unsigned* p, unsigned old, int limit, unsigned* err) {
+    for (int n = 0; ld_agent(p) == old; ++n) {
+        if (n >= limit) {
+            __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+struct BarCtx {
+    int xcd;        // this block's XCD
+    unsigned gsz;   // blocks of the launch on that XCD
+    unsigned nxcd;  // XCDs holding blocks of the launch
+};
+
+// Kernel start: count the blocks per XCD (one barrier on atomics only; no
+// data is exchanged through it).
+__device__ bool bar_setup(FusedBarrier* bar, int limit, BarCtx& bc) {
     __shared__ int ok;
+    __shared__ unsigned sg, sn;
+    __shared__ int sx;
+    if (threadIdx.x == 0) {
+        unsigned* err = bar_word(bar, 2);
+        const int x = __builtin_amdgcn_s_getreg(20 | (3 << 11)) & (kBarXcds - 1);  // XCC_ID[3:0]
+        int good = ld_agent(err) == 0;
+        if (good) {
+            arrived(add_agent(bar_word(bar, 3 + x), 1u));
+            const unsigned g = ld_agent(bar_word(bar, 1));
+            arrived(g);
+            if (add_agent(bar_word(bar, 0), 1u) + 1u == gridDim.x) {
+                st_agent(bar_word(bar, 0), 0u);
+                add_agent(bar_word(bar, 1), 1u);
+            } else {
+                good = bar_wait(bar_word(bar, 1), g, limit, err);
+            }
+        }
+        unsigned n = 0;
+        for (int i = 0; i < kBarXcds; ++i) n += ld_agent(bar_word(bar, 3 + i)) ? 1u : 0u;
+        sg = ld_agent(bar_word(bar, 3 + x));
+        sn = n;
+        sx = x;
+        ok = good;
+    }
+    __syncthreads();
+    bc.xcd = sx;
+    bc.gsz = sg;
+    bc.nxcd = sn;
+    return ok != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(FusedBarrier* bar, const BarCtx& bc, int limit) {
+    __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the L2
     __syncthreads();
     if (threadIdx.x == 0) {
-        int good = __hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        unsigned* err = bar_word(bar, 2);
+        int good = ld_agent(err) == 0;
         if (good) {
-            const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
-                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (arrived == nblocks) {
-                __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                int polls = 0;
-                while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                    if (++polls > limit) {
-                        __hip_atomic_fetch_or(&bar->err, 1, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                        good = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
+            unsigned* cnt = bar_word(bar, 3 + kBarXcds + bc.xcd);
+            unsigned* flag = bar_word(bar, 3 + 2 * kBarXcds + bc.xcd);
+            const unsigned f = ld_agent(flag);
+            arrived(f);  // read before arriving: the flag cannot move until then
+            if (add_agent(cnt, 1u) + 1u == bc.gsz) {
+                // leader: the XCD's writes to memory, then the grid-wide arrival
+                st_agent(cnt, 0u);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const unsigned g = ld_agent(bar_word(bar, 1));
+                arrived(g);
+                if (add_agent(bar_word(bar, 0), 1u) + 1u == bc.nxcd) {
+                    st_agent(bar_word(bar, 0), 0u);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    add_agent(bar_word(bar, 1), 1u);
+                } else {
+                    good = bar_wait(bar_word(bar, 1), g, limit, err);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the XCD's L2 and this L1
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // invalidate done before the flag
+                st_agent(flag, f + 1u);
+            } else {
+                good = bar_wait(flag, f, limit, err);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // this CU's L1 (and the L2)
             }
-            __threadfence();
         }
         ok = good;
     }
@@ -535,6 +619,9 @@ __global__ __launch_bounds__(256) void kf_step(const Item<T>* __restrict__ items
                                                const FusedPhase* __restrict__ phases, int nphase,
                                                FusedBarrier* bar, int limit) {
     const unsigned nb = gridDim.x;
+    if (nphase <= 0) return;
+    BarCtx bc;
+    if (!bar_setup(bar, limit, bc)) return;
     for (int t = 0; t < nphase; ++t) {
         for (int k = 0; k < KC_N; ++k) {
             const FusedPhase P = phases[t * KC_N + k];
@@ -562,9 +649,12 @@ __global__ __launch_bounds__(256) void kf_step(const Item<T>* __restrict__ items
                     run_aux(w.aux, (j - w.nblk) * (int)blockDim.x + threadIdx.x);
                 }
             }
-            if (!grid_barrier(bar, nb, limit)) return;
+            if (!grid_barrier(bar, bc, limit)) return;
         }
     }
+    // every block has passed the last barrier, so the counts are no longer
+    // read: clear them for the next launch
+    if (blockIdx.x == 0 && threadIdx.x < kBarXcds) st_agent(bar_word(bar, 3 + threadIdx.x), 0u);
 }
 
 // Diagnostics: block partials [mass, energy, -h_min, h_max, |u|max, nonfinite]

@@ -729,25 +729,36 @@ __global__ void k_gate(const T* __restrict__ h0, const T* __restrict__ u0,
         a[4] = (double)R0u[e] * (double)R0u[e];
         a[5] = (double)R1u[e] * (double)R1u[e];
     }
-    __shared__ double sm[256];
-    for (int k = 0; k < 6; ++k) {
-        sm[threadIdx.x] = a[k];
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[blockIdx.x * 6 + k] = sm[0];
+    // one fixed-order tree over the block for all six sums
+    __shared__ double red[6][256];
+    const int i = threadIdx.x;
+    for (int k = 0; k < 6; ++k) red[k][i] = a[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (i < w)
+            for (int k = 0; k < 6; ++k) red[k][i] += red[k][i + w];
         __syncthreads();
     }
+    if (i < 6) part[blockIdx.x * 6 + i] = red[i][0];
 }
 
-__global__ void k_gate_final(const double* __restrict__ part, int nparts, double* __restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= 6) return;
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[b * 6 + k];
-    out[k] = s;
+// Totals of the per-block partials: 256 strided sums, then a tree, all in a
+// fixed order (the gate value does not depend on timing).
+__global__ __launch_bounds__(256) void k_gate_final(const double* __restrict__ part, int nparts,
+                                                    double* __restrict__ out) {
+    __shared__ double red[6][256];
+    const int i = threadIdx.x;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = i; b < nparts; b += 256)
+        for (int k = 0; k < 6; ++k) v[k] += part[(size_t)b * 6 + k];
+    for (int k = 0; k < 6; ++k) red[k][i] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (i < w)
+            for (int k = 0; k < 6; ++k) red[k][i] += red[k][i + w];
+        __syncthreads();
+    }
+    if (i < 6) out[i] = red[i][0];
 }
 
 }  // namespace
@@ -940,7 +951,7 @@ void gate_sums(const T* h0, const T* u0, const T* h1, const T* u1, const T* R0h,
     if (n == 0) return;
     hipLaunchKernelGGL((k_gate<T>), dim3(n), dim3(256), 0, s, h0, u0, h1, u1, R0h, R0u, R1h, R1u,
                        nF, nFe, dt, part);
-    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, s, (const double*)part, (int)n, out);
+    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(256), 0, s, (const double*)part, (int)n, out);
 }
 
 #define LTS_NN_INSTANTIATE(T)                                                                    \

@@ -1051,6 +1051,47 @@ def bench_surrogate(args):
             continue
         log(f"{name}: {ms:.2f} ms, accepted {acc[0]}/{K}, err {runs[name]['err']:.3e}, "
             f"mass defect {runs[name]['mass_rel_defect']:.2e}")
+    # roofline of the step's dominant kernel: every step accepted (tau
+    # infinite) from the held-out state, launched with event-stamped passes
+    # (the context's timing mode); one discarded pass, then three
+    n_t = min(8, K)
+    roofline = None
+    try:
+        ctx.set_timing(True)
+        for rep in range(4):
+            if rep == 1:
+                ctx.set_timing(True)   # restart the statistics after the discarded pass
+            ctx.init_state(*init(ev))
+            sur.step(dt, M, n_t, tau=1e30)
+            stats = ctx.kernel_stats()
+        dom = max(stats, key=lambda k: stats[k]["ms"])
+        st = stats[dom]
+        avg_ms = st["ms"] / st["launches"]
+        bpl = st["bytes"] / st["launches"]
+        achieved = bpl / (avg_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": dom, "launches": st["launches"], "avg_us": round(avg_ms * 1e3, 2),
+                    "bytes_per_launch": round(bpl),
+                    "note": "right-hand-side passes of accepted surrogate steps (R(x_n) and "
+                            "R(x_new) on F, Steps 1, 2 and 4); the network's kernels are timed "
+                            "by --workload gemm"}
+        log(f"surrogate step kernels: {json.dumps(stats)}")
+    except lts.LTSError as ex:   # the ungated steps left non-finite values
+        log(f"surrogate step timing: {ex}")
+    ctx.set_timing(False)
+    # CPU baseline: the oracle has no surrogate; its LTS3 (the method the gate
+    # falls back to) on the same mesh, all host threads and one
+    th = host_cores()
+    va, na, ta, _, tha = oracle_baseline(w, m.nCells * M, th, args.cpu_seconds)
+    v1, n1, t1, _, _ = oracle_baseline(w, m.nCells * M, 1, args.cpu_seconds)
+    cpu = {"value": round(va, 1), "unit": "cell-updates/s", "cores": tha, "kind": "oracle",
+           "sample": f"the oracle's LTS3 (it has no surrogate step; LTS3 is the method the "
+                     f"gate falls back to): {na} coarse steps (M={M}) of {w.name} in "
+                     f"{ta:.1f}s on {tha} threads",
+           "single_thread": {"value": round(v1, 1), "cores": 1,
+                             "sample": f"{n1} coarse steps in {t1:.1f}s, one thread"}}
+    log(f"cpu baseline: {cpu}")
     base = runs["lts3_dt_x1"]
     g = runs["surrogate_gated"]
     eps = g["err"]
@@ -1080,7 +1121,7 @@ def bench_surrogate(args):
            "gain_same_dt": round(base["ms"] / g_ms, 3),
            "gain_time_to_solution": round(best / g_ms, 3) if best else None,
            "gain_time_to_solution_vs_rk3_fp64": round(best_rk / g_ms, 3) if best_rk else None,
-           "epsilon": eps}
+           "epsilon": eps, "roofline": roofline, "cpu_baseline": cpu}
     sur.close()
     ctx.close()
     emit(out)

@@ -126,7 +126,11 @@ lts_status lts_sur_predict(lts_sur *s, float *out_h, float *out_u);
    (-1 for a skipped step; either may be NULL) report the outcome.
    Synchronises once per attempted step.  The first call with a new (dt, M)
    allocates the 3M-layer stage buffers of the interface accumulation and
-   captures the step's graph. */
+   captures the step's graph.  While the context is in timing mode
+   (lts_set_timing), each attempted step is launched rather than replayed and
+   its right-hand-side passes (vertex, cell and edge kernels of R(x_n) and
+   R(x_new) on F and of Steps 1, 2 and 4) are event-stamped into
+   lts_kernel_stats, as are the fallback steps. */
 lts_status lts_sur_step(lts_sur *s, double dt, int M, int n_steps, double tau, int max_backoff,
                         int *n_accepted, double *residuals);
 

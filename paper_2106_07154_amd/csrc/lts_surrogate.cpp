@@ -332,10 +332,10 @@ void features_of_state(lts_sur* s, float* raw) {
 
 // R(x) on the fine cells and fine edges into (Rh, Ru).
 template <typename T>
-lts_status fine_rhs(lts_sur* s, const T* h, const T* u, T* Rh, T* Ru) {
+lts_status fine_rhs(lts_sur* s, const T* h, const T* u, T* Rh, T* Ru, bool timed = false) {
     lts_ctx* c = s->c;
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
-    Run<T> r{c, dm, s->s, false};
+    Run<T> r{c, dm, s->s, timed};
     const Seg<T> none;
     return r.pass(P_STEP3, h, u, Run<T>::upd(0, c->cb[3], Rh, nullptr, 0, nullptr, 0, 1.0), none,
                   Run<T>::upd(0, c->eb[2], Ru, nullptr, 0, nullptr, 0, 1.0), none);
@@ -369,12 +369,14 @@ lts_status record_typed(lts_sur* s, double dt, int M, int n) {
 // fine stages at once (F read linearly in time between x_n and the
 // prediction, I1 predicted, I2 and C at the coarse stages), Step 4 on C,
 // Step 5 on I.  Then the mass change of the whole step is removed from F as
-// a uniform thickness shift, so mass is conserved to rounding.
+// a uniform thickness shift, so mass is conserved to rounding.  With timed,
+// the right-hand-side passes are event-stamped (the context's timing mode;
+// the step is then launched directly, not captured).
 template <typename T>
-lts_status enqueue_sur_step(lts_sur* s, double dt, int M) {
+lts_status enqueue_sur_step(lts_sur* s, double dt, int M, bool timed = false) {
     lts_ctx* c = s->c;
     const DevMesh<T>& dm = *static_cast<DevMesh<T>*>(c->dm);
-    Run<T> r{c, dm, s->s, false};
+    Run<T> r{c, dm, s->s, timed};
     T *Ah = (T*)c->Ah, *Au = (T*)c->Au, *Bh = (T*)c->Bh, *Bu = (T*)c->Bu, *Ch = (T*)c->Ch,
       *Cu = (T*)c->Cu;
     T *R0h = (T*)s->R0h, *R0u = (T*)s->R0u, *R1h = (T*)s->R1h, *R1u = (T*)s->R1u;
@@ -387,7 +389,7 @@ lts_status enqueue_sur_step(lts_sur* s, double dt, int M) {
     SCHK(s, hipMemcpyAsync(Sh, Ah, nC * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     SCHK(s, hipMemcpyAsync(Su, Au, nE * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     // R(x_n) on F
-    if ((st = fine_rhs<T>(s, Ah, Au, R0h, R0u))) return st;
+    if ((st = fine_rhs<T>(s, Ah, Au, R0h, R0u, timed))) return st;
     // F at t + dt: a forward-Euler step plus the network's correction
     features_of_state<T>(s, s->raw);
     nn::norm_features(s->raw, s->N, s->norm, s->norm + 5, s->X, s->s);
@@ -440,7 +442,7 @@ lts_status enqueue_sur_step(lts_sur* s, double dt, int M) {
     SCHK(s, hipMemcpyAsync(Au, Pu, s->nFe * sizeof(T), hipMemcpyDeviceToDevice, s->s));
     nn::mass_fix<T>(dm.area, Sh, Ah, nC, s->nF, s->inv_area_f, s->mpart, s->mshift, s->s);
     // R(x_new) on F and the residual sums
-    if ((st = fine_rhs<T>(s, Ah, Au, R1h, R1u))) return st;
+    if ((st = fine_rhs<T>(s, Ah, Au, R1h, R1u, timed))) return st;
     nn::gate_sums<T>((const T*)Sh, (const T*)Su, Ah, Au, R0h, R0u, R1h, R1u, s->nF, s->nFe, dt,
                      s->dpart, s->gout, s->s);
     return LTS_OK;
@@ -492,7 +494,15 @@ lts_status sur_step_typed(lts_sur* s, double dt, int M, int n, double tau, int m
                 return sfail(s, st, std::string("LTS3 step: ") + lts_last_error(c));
             continue;
         }
-        SCHK(s, hipGraphLaunch(s->gexec, s->s));
+        if (c->timing) {  // event-stamped passes: the step is launched, not replayed
+            int* saved = c->flag;
+            c->flag = s->flag;
+            st = enqueue_sur_step<T>(s, dt, M, true);
+            c->flag = saved;
+            if (st) return sfail(s, st, std::string("surrogate step: ") + c->err);
+        } else {
+            SCHK(s, hipGraphLaunch(s->gexec, s->s));
+        }
         SCHK(s, hipMemcpyAsync(s->host4, s->gout, 6 * sizeof(double), hipMemcpyDeviceToHost, s->s));
         SCHK(s, hipStreamSynchronize(s->s));
         const double* o = s->host4;

@@ -394,6 +394,36 @@ def test_surrogate_steps_conserve_mass(igw):
     assert d.n_nonfinite == 0 and abs(d.mass - m0) / m0 < 1e-13
 
 
+def test_timed_surrogate_step_matches_replayed_graph(igw):
+    """In the context's timing mode a surrogate step is launched pass by pass
+    with event stamps instead of replaying its graph: the same states and gate
+    values bitwise, and five right-hand-side passes per step (R(x_n) and
+    R(x_new) on F, Steps 1, 2 and 4) in the kernel statistics."""
+    w = igw
+    say("surrogate timing mode", w.name)
+    a, b = _ctx(w), _ctx(w)
+    sa, sb = lts.Surrogate(a, seed=11), lts.Surrogate(b, seed=11)
+    norm = np.array([0] * 5 + [1] * 7 + [1e-3, 1e-3, 0, 0], np.float32)
+    sa.set_norm(norm)
+    sb.set_norm(norm)
+    acc_a, ra = sa.step(w.dt_coarse, w.M, 3, tau=1e30)
+    b.set_timing(True)
+    acc_b, rb = sb.step(w.dt_coarse, w.M, 3, tau=1e30)
+    st = b.kernel_stats()
+    b.set_timing(False)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert acc_a == acc_b == 3
+    assert np.array_equal(ra, rb)
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    for k in ("vertex_pv", "cell_tendency", "edge_tendency"):
+        assert st[k]["launches"] == 15 and st[k]["ms"] > 0 and st[k]["bytes"] > 0, (k, st[k])
+    sa.close()
+    sb.close()
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_gate_rejects_fall_back_to_lts3_bitwise(igw, prec):
     w = igw

@@ -404,6 +404,39 @@ lts_status build_device(lts_ctx* c, const lts_mesh* m) {
     if ((s = upload_vec<T>(c, &dm->nd, conv<T>(nd)))) return s;
     if ((s = upload_vec<T>(c, &dm->kc, conv<T>(kc)))) return s;
     if ((s = upload_vec<T>(c, &dm->kf, conv<T>(kf)))) return s;
+    dm->pG = 0;
+    dm->peoc = dm->pcoc = dm->pvoc = nullptr;
+    dm->pnl = dm->pnd = dm->pkc = dm->pkf = nullptr;
+    if (c->L > 1) {  // padded copies for the layered cell kernel
+        const int G = padded_slots(c->maxE);
+        const size_t np = (size_t)nC * G;
+        std::vector<int32_t> pe(np), pc(np), pv(np);
+        std::vector<double> pnl(np, 0.0), pnd(np, 0.0), pkc(np, 0.0), pkf(np, 0.0);
+        for (int ni = 0; ni < nC; ++ni) {
+            const size_t o0 = (size_t)cso[2 * (size_t)ni];
+            const int n = nEoC[ni];
+            for (int a = 0; a < G; ++a) {
+                const size_t o = o0 + std::min(a, n - 1), d = (size_t)ni * G + a;
+                pe[d] = eoc[o];
+                pc[d] = coc[o];
+                pv[d] = voc[o];
+                if (a < n) {
+                    pnl[d] = nl[o];
+                    pnd[d] = nd[o];
+                    pkc[d] = kc[o];
+                    pkf[d] = kf[o];
+                }
+            }
+        }
+        dm->pG = G;
+        if ((s = upload_vec<int32_t>(c, &dm->peoc, pe))) return s;
+        if ((s = upload_vec<int32_t>(c, &dm->pcoc, pc))) return s;
+        if ((s = upload_vec<int32_t>(c, &dm->pvoc, pv))) return s;
+        if ((s = upload_vec<T>(c, &dm->pnl, conv<T>(pnl)))) return s;
+        if ((s = upload_vec<T>(c, &dm->pnd, conv<T>(pnd)))) return s;
+        if ((s = upload_vec<T>(c, &dm->pkc, conv<T>(pkc)))) return s;
+        if ((s = upload_vec<T>(c, &dm->pkf, conv<T>(pkf)))) return s;
+    }
     if ((s = upload_vec<T>(c, &dm->sb, conv<T>(sb)))) return s;
     if ((s = upload_vec<T>(c, &dm->sn, conv<T>(sn)))) return s;
     if ((s = upload_vec<T>(c, &dm->area, conv<T>(area)))) return s;

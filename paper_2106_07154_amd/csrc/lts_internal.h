@@ -55,6 +55,14 @@ struct DevMesh {
     const T* tdc;          // [3][nV] t_{e,v} d_e
     const T* kite;         // [3][nV] A_{i,v}
     const T* fA;           // [nV] f_v A_v
+    // Layered contexts (L > 1) also keep the slot tables the layered cell
+    // kernel reads padded to pG = padded_slots(maxE) entries per cell (cell i
+    // at i pG; padding entries repeat the last slot's indices with zero
+    // coefficients), so its table addresses follow from i alone instead of
+    // waiting for cso[i].  Null otherwise.
+    int pG;
+    const int32_t *peoc, *pcoc, *pvoc;
+    const T *pnl, *pnd, *pkc, *pkf;
 };
 
 // One epilogue segment: targets [lo, hi) of a tendency kernel.

@@ -842,8 +842,10 @@ __global__ __launch_bounds__(kBlock) void k_vertex_l(DevMesh<T> m, const T* __re
 }
 
 // The cell's slots in a loop, with the same O(n) prefix-sum form of the PV
-// share as the single-layer cell kernel.
-template <typename T, int G, bool W, int HR>
+// share as the single-layer cell kernel.  PAD: the padded slot tables of a
+// layered context (addresses from i alone); otherwise the compact ones
+// (the surrogate's interface pass on a single-layer context).
+template <typename T, int G, bool W, int HR, bool PAD>
 __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __restrict__ h,
                                                    const T* __restrict__ u,
                                                    const T* __restrict__ q,
@@ -854,21 +856,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     bool act;
     layer_slot<W>(c_lo, L, i, l, act);
     if (i >= c_hi) return;
-    const int32_t* __restrict__ eoc = m.eoc;
-    const int32_t* __restrict__ coc = m.coc;
-    const int32_t* __restrict__ voc = m.voc;
-    const T* __restrict__ nl = m.nl;
-    const T* __restrict__ nd = m.nd;
-    const T* __restrict__ kc = m.kc;
-    const T* __restrict__ kf = m.kf;
+    const int32_t* __restrict__ eoc = PAD ? m.peoc : m.eoc;
+    const int32_t* __restrict__ coc = PAD ? m.pcoc : m.coc;
+    const int32_t* __restrict__ voc = PAD ? m.pvoc : m.voc;
+    const T* __restrict__ nl = PAD ? m.pnl : m.nl;
+    const T* __restrict__ nd = PAD ? m.pnd : m.nd;
+    const T* __restrict__ kc = PAD ? m.pkc : m.kc;
+    const T* __restrict__ kf = PAD ? m.pkf : m.kf;
     const T* __restrict__ href = m.href;
-    const int2 so = m.cso[i];
+    const int2 so = PAD ? int2{0, m.nEoC[i]} : m.cso[i];
     const int n = so.y;
+    const size_t base = PAD ? (size_t)i * G : (size_t)so.x;
     const size_t il = (size_t)i * L + l;
     const bool hr = present<HR>(href);
     const T hi = hr ? href[i] + h[il] : h[il];
     // PV of the last slot's vertex: the predecessor of slot 0
-    T qprev = q[(size_t)voc[(size_t)so.x + n - 1] * L + l];
+    T qprev = q[(size_t)voc[base + n - 1] * L + l];
     // Every slot up to G, padding included: padding slots re-read the last
     // slot with its coefficients zeroed, so they add exact zeros to the sums
     // and only their stores are skipped.  Without a branch per slot all the
@@ -877,8 +880,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     T K = 0, S = 0, t1 = 0, t2 = 0, p1 = 0, p2 = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        const bool real = a < n;
-        const size_t o = (size_t)so.x + min(a, n - 1);
+        const bool real = PAD || a < n;  // padded tables hold zero coefficients
+        const size_t o = base + (PAD ? a : min(a, n - 1));
         const int e = eoc[o], nb = coc[o];
         const T ue = u[(size_t)e * L + l];
         const T hn0 = h[(size_t)nb * L + l];
@@ -902,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
     T c1 = 0, c2 = 0, Sr = 0;
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        const size_t o = (size_t)so.x + min(a, n - 1);
+        const size_t o = base + (PAD ? a : min(a, n - 1));
         const T Sb = Sr;
         Sr += kfA[a];
         c1 += X1[a];
@@ -1018,15 +1021,18 @@ hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q
     if (c_hi <= c_lo) return hipSuccess;
     const dim3 grid(nblocks(layer_threads(c_hi - c_lo, L)));
     const bool w = wave_layers(L), g8 = padded_slots(m.maxE) == 8;
-#define LTS_CELL_L(GG, W, HR)                                                                    \
-    launch(k_cell_l<T, GG, W, HR>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0, s1,  \
-           flag)
+    const bool pad = m.peoc != nullptr && m.pG == padded_slots(m.maxE);
+#define LTS_CELL_L(GG, W, HR, P)                                                                 \
+    launch(k_cell_l<T, GG, W, HR, P>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, L, g, s0,   \
+           s1, flag)
+#define LTS_CELL_LP(GG, W, HR) (pad ? LTS_CELL_L(GG, W, HR, true) : LTS_CELL_L(GG, W, HR, false))
     if (m.href) {
-        if (w) return g8 ? LTS_CELL_L(8, true, 1) : LTS_CELL_L(16, true, 1);
-        return g8 ? LTS_CELL_L(8, false, 1) : LTS_CELL_L(16, false, 1);
+        if (w) return g8 ? LTS_CELL_LP(8, true, 1) : LTS_CELL_LP(16, true, 1);
+        return g8 ? LTS_CELL_LP(8, false, 1) : LTS_CELL_LP(16, false, 1);
     }
-    if (w) return g8 ? LTS_CELL_L(8, true, 0) : LTS_CELL_L(16, true, 0);
-    return g8 ? LTS_CELL_L(8, false, 0) : LTS_CELL_L(16, false, 0);
+    if (w) return g8 ? LTS_CELL_LP(8, true, 0) : LTS_CELL_LP(16, true, 0);
+    return g8 ? LTS_CELL_LP(8, false, 0) : LTS_CELL_LP(16, false, 0);
+#undef LTS_CELL_LP
 #undef LTS_CELL_L
 }
 

@@ -58,7 +58,25 @@ def strict(x):
     return x
 
 
+def host_cpu():
+    """The host the CPU baseline ran on: processor model and the threads the
+    machine reports (the baseline's own thread count is its "cores")."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def emit(out):
+    cb = out.get("cpu_baseline")
+    if isinstance(cb, dict) and "host" not in cb:
+        cb["host"] = host_cpu()
     print(json.dumps(strict(out), allow_nan=False), flush=True)
 
 

@@ -96,6 +96,16 @@ typedef struct {
     const int32_t *n_edges_on_edge;      /* [n_edges]                          */
     const int32_t *edges_on_edge;        /* [n_edges][max_edges2]              */
     const double *weights_on_edge;       /* [n_edges][max_edges2]              */
+    /* Optional sign tables (each NULL or given).  The library derives both
+       signs from the orientation convention above and never reads these in
+       a step; given tables are checked against it: edge_sign_on_cell[i][j]
+       must be n_{e,i} of e = edges_on_cell[i][j] (+1 when cells_on_edge[e][0]
+       is i, else -1) and edge_sign_on_vertex[v][k] must be t_{e,v} of
+       e = edges_on_vertex[v][k] (+1 when vertices_on_edge[e][1] is v, else
+       -1).  A mismatch is LTS_EMESH naming the cell or vertex.  (A table
+       with the opposite convention is the negation of these.) */
+    const int8_t *edge_sign_on_cell;     /* [n_cells][max_edges]               */
+    const int8_t *edge_sign_on_vertex;   /* [n_vertices][3]                    */
 } lts_mesh;
 
 typedef struct {

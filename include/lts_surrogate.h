@@ -80,6 +80,17 @@ lts_status lts_sur_get_norm(const lts_sur *s, float *norm16);
 lts_status lts_sur_get_params(const lts_sur *s, float *p);
 lts_status lts_sur_set_params(lts_sur *s, const float *p);
 
+/* Save the network to the file `path` (its shape, the normalisation vector
+   when one is set, and the parameters; FP32, little-endian), or load a file
+   written by lts_sur_save into a surrogate of the same shape, on any context
+   and mesh (the parameters do not depend on the mesh).  Loading sets the
+   normalisation vector when the file holds one and resets the Adam state;
+   recorded training samples are not part of the file.  LTS_EINVAL for a file
+   that cannot be opened or written, is not such a file, is truncated or
+   longer, or has another shape. */
+lts_status lts_sur_save(const lts_sur *s, const char *path);
+lts_status lts_sur_load(lts_sur *s, const char *path);
+
 /* n_iters Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8), step i on the
    recorded sample idx[i].  Loss per step = mean over fine cells of
    (out_h - th/rms_h)^2 + mean over fine edges of (out_u - tu/rms_u)^2 with

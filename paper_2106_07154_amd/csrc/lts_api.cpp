@@ -133,6 +133,34 @@ lts_status check_weights(lts_ctx* c, const lts_mesh* m) {
     return LTS_OK;
 }
 
+// Caller's sign tables (optional) against the orientation convention:
+// n_{e,i} = +1 when i = cells_on_edge[e][0], t_{e,v} = +1 when
+// v = vertices_on_edge[e][1].  Runs after the connectivity checks.
+lts_status check_signs(lts_ctx* c, const lts_mesh* m) {
+    if (m->edge_sign_on_cell)
+        for (int i = 0; i < m->n_cells; ++i)
+            for (int j = 0; j < m->n_edges_on_cell[i]; ++j) {
+                const size_t o = (size_t)i * m->max_edges + j;
+                const int e = m->edges_on_cell[o];
+                const int want = m->cells_on_edge[2 * e] == i ? 1 : -1;
+                if (m->edge_sign_on_cell[o] != want)
+                    return fail(c, LTS_EMESH,
+                                "edge_sign_on_cell differs from the orientation of cells_on_edge "
+                                "at cell " + std::to_string(i));
+            }
+    if (m->edge_sign_on_vertex)
+        for (int v = 0; v < m->n_vertices; ++v)
+            for (int k = 0; k < 3; ++k) {
+                const int e = m->edges_on_vertex[3 * v + k];
+                const int want = m->vertices_on_edge[2 * e + 1] == v ? 1 : -1;
+                if (m->edge_sign_on_vertex[3 * v + k] != want)
+                    return fail(c, LTS_EMESH,
+                                "edge_sign_on_vertex differs from the orientation of "
+                                "vertices_on_edge at vertex " + std::to_string(v));
+            }
+    return LTS_OK;
+}
+
 lts_status validate(lts_ctx* c, const lts_mesh* m) {
     const int nC = m->n_cells, nE = m->n_edges, nV = m->n_vertices, mx = m->max_edges;
     if (nC < 3 || nE < 3 || nV < 3 || mx < 3)
@@ -194,7 +222,8 @@ lts_status validate(lts_ctx* c, const lts_mesh* m) {
                 return fail(c, LTS_EMESH, "non-positive kite area");
         }
     }
-    return check_weights(c, m);
+    lts_status st = check_signs(c, m);
+    return st ? st : check_weights(c, m);
 }
 
 // ---------------------------------------------------------------- regions

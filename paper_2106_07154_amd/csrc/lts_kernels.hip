@@ -343,24 +343,31 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
     cell_math<T, G, PRE>(m, c, q[m.voc[c.o]], zs, g, s0, s1, flag);
 }
 
-// Cells with more than 8 edges are not handled by their 8-lane groups (their
-// lanes are dead, see cell_loads): nbw blocks appended to the launch take
-// them from the mesh's list of such cells (entries [w_lo, w_hi)), 16 lanes
-// each, so a mesh with a few wide cells keeps 8 lanes everywhere else and
-// needs no extra launch.  The appended branch costs scalar registers (106
-// against 74, one wave per SIMD less), so it is compiled in (WIDE) only for
-// meshes that have such cells.
-template <typename T, int HR, bool WIDE>
+// The cell kernel: 8 lanes per cell over [c_lo, c_hi), blocks spread over
+// the 8 XCDs (xcd_block).
+template <typename T, int HR>
 __global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ q, T* __restrict__ zs,
                                                  int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
-                                                 int* flag, int nbc, int w_lo, int w_hi) {
-    if (!WIDE) {
-        cell_body<T, 8, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi,
-                                  g, s0, s1, flag);
-        return;
-    }
+                                                 int* flag) {
+    cell_body<T, 8, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
+                              s0, s1, flag);
+}
+
+// Meshes with cells of more than 8 edges: those cells are not handled by
+// their 8-lane groups (their lanes are dead, see cell_loads); nbw blocks
+// appended to the launch take them from the mesh's list of such cells
+// (entries [w_lo, w_hi)), 16 lanes each, so the other cells keep 8 lanes and
+// no extra launch is needed.  The appended branch needs more scalar
+// registers (106 against 74, which would cost a wave per SIMD); the
+// waves-per-EU bound keeps the kernel at 8 waves per SIMD (a few scalar
+// values then live in vector-register lanes).
+template <typename T, int HR>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cell_wide(
+    DevMesh<T> m, const T* __restrict__ h, const T* __restrict__ u, const T* __restrict__ q,
+    T* __restrict__ zs, int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1, int* flag, int nbc,
+    int w_lo, int w_hi) {
     const int b = blockIdx.x;
     if (b >= nbc) {
         const int t = (b - nbc) * kBlock + threadIdx.x;
@@ -970,13 +977,18 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
     if (c_hi <= c_lo) return hipSuccess;
     const int nbc = (int)nblocks((long)(c_hi - c_lo) * 8);
     const int nbw = w_hi > w_lo ? (int)nblocks((long)(w_hi - w_lo) * 16) : 0;
-    const dim3 grid(nbc + nbw);
-#define LTS_CELL(HR, W) \
-    launch(k_cell<T, HR, W>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag, nbc, \
-           w_lo, w_hi)
-    if (m.href) return nbw ? LTS_CELL(1, true) : LTS_CELL(1, false);
-    return nbw ? LTS_CELL(0, true) : LTS_CELL(0, false);
-#undef LTS_CELL
+    if (nbw) {
+        const dim3 grid(nbc + nbw);
+        if (m.href)
+            return launch(k_cell_wide<T, 1>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0,
+                          s1, flag, nbc, w_lo, w_hi);
+        return launch(k_cell_wide<T, 0>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1,
+                      flag, nbc, w_lo, w_hi);
+    }
+    const dim3 grid(nbc);
+    if (m.href)
+        return launch(k_cell<T, 1>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
+    return launch(k_cell<T, 0>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
 }
 
 template <typename T>

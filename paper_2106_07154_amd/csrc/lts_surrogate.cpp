@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -728,6 +729,46 @@ lts_status lts_sur_set_params(lts_sur* s, const float* p) {
     refresh_bf16(s);
     SCHK(s, hipStreamSynchronize(s->s));
     return LTS_OK;
+}
+
+// File layout (little-endian): 8-byte tag, int32 n_layers, hidden,
+// n_params, has_norm, then float norm[16] and float params[n_params].
+static const char kSurTag[8] = {'L', 'T', 'S', 'S', 'U', 'R', '0', '1'};
+
+lts_status lts_sur_save(const lts_sur* s, const char* path) {
+    if (!s || !path) return LTS_EINVAL;
+    std::vector<float> p(N_PARAMS);
+    lts_status st = lts_sur_get_params(s, p.data());
+    if (st) return st;
+    const int32_t hdr[4] = {kLayers, nn::kHid, N_PARAMS, s->has_norm ? 1 : 0};
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return LTS_EINVAL;
+    bool ok = std::fwrite(kSurTag, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 &&
+              std::fwrite(s->norm_host, 4, 16, f) == 16 &&
+              std::fwrite(p.data(), 4, N_PARAMS, f) == (size_t)N_PARAMS;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? LTS_OK : LTS_EINVAL;
+}
+
+lts_status lts_sur_load(lts_sur* s, const char* path) {
+    if (!s || !path) return LTS_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return sfail(s, LTS_EINVAL, std::string("cannot open ") + path);
+    char tag[8];
+    int32_t hdr[4];
+    float nrm[16];
+    std::vector<float> p(N_PARAMS);
+    bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kSurTag, 8) == 0 &&
+              std::fread(hdr, 4, 4, f) == 4 && hdr[0] == kLayers && hdr[1] == nn::kHid &&
+              hdr[2] == N_PARAMS && std::fread(nrm, 4, 16, f) == 16 &&
+              std::fread(p.data(), 4, N_PARAMS, f) == (size_t)N_PARAMS;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    std::fclose(f);
+    if (!ok) return sfail(s, LTS_EINVAL, std::string("not a surrogate file of this shape: ") + path);
+    lts_status st;
+    if (hdr[3] && (st = lts_sur_set_norm(s, nrm))) return st;
+    return lts_sur_set_params(s, p.data());
 }
 
 lts_status lts_sur_train(lts_sur* s, const int32_t* idx, int n, float lr, float* losses) {

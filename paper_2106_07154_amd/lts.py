@@ -33,7 +33,8 @@ EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_upload_mesh_
             "lts_ens_last_error", "lts_ens_destroy",
             "lts_sur_create", "lts_sur_info", "lts_sur_node_map", "lts_sur_record",
             "lts_sur_normalize", "lts_sur_set_norm", "lts_sur_get_norm", "lts_sur_get_params",
-            "lts_sur_set_params", "lts_sur_train", "lts_sur_grad", "lts_sur_features",
+            "lts_sur_set_params", "lts_sur_save", "lts_sur_load", "lts_sur_train",
+            "lts_sur_grad", "lts_sur_features",
             "lts_sur_predict", "lts_sur_step", "lts_sur_last_error", "lts_sur_destroy",
             "lts_nn_gemm_bf16", "lts_nn_gemm_tn_bf16", "lts_nn_gemm_bf16_device",
             "lts_nn_gemm_tn_bf16_device_noalloc", "lts_nn_gemm_tn_noalloc_max_rows"]
@@ -54,7 +55,8 @@ class _Mesh(ctypes.Structure):
             "kite_areas_on_vertex", "area_cell", "area_triangle", "dc_edge", "dv_edge",
             "f_vertex", "bottom", "cell_xyz")] + [
         ("max_edges2", ctypes.c_int32), ("n_edges_on_edge", ctypes.c_void_p),
-        ("edges_on_edge", ctypes.c_void_p), ("weights_on_edge", ctypes.c_void_p)]
+        ("edges_on_edge", ctypes.c_void_p), ("weights_on_edge", ctypes.c_void_p),
+        ("edge_sign_on_cell", ctypes.c_void_p), ("edge_sign_on_vertex", ctypes.c_void_p)]
 
 
 class _Diag(ctypes.Structure):
@@ -139,6 +141,8 @@ def load_library(path: str = LIB_PATH):
         "lts_sur_get_norm": ([P, P], ci),
         "lts_sur_get_params": ([P, P], ci),
         "lts_sur_set_params": ([P, P], ci),
+        "lts_sur_save": ([P, ctypes.c_char_p], ci),
+        "lts_sur_load": ([P, ctypes.c_char_p], ci),
         "lts_sur_train": ([P, P, ci, ctypes.c_float, P], ci),
         "lts_sur_grad": ([P, ci, P, P], ci),
         "lts_sur_features": ([P, P], ci),
@@ -200,8 +204,9 @@ class LTSContext:
 
     # ---------------------------------------------------------------- mesh
     def upload_mesh(self, mesh, fine_mask, n_if1: int = 2, n_if2: int = 2,
-                    gravity: float = 9.81, use_positions: bool = True, edge_weights=None):
-        m, keep = _mesh_struct(mesh, use_positions, edge_weights)
+                    gravity: float = 9.81, use_positions: bool = True, edge_weights=None,
+                    edge_signs=None):
+        m, keep = _mesh_struct(mesh, use_positions, edge_weights, edge_signs)
         fm = np.ascontiguousarray(fine_mask, np.uint8)
         self._check(self._lib.lts_upload_mesh(self._h, ctypes.byref(m), _ptr(fm), int(n_if1),
                                               int(n_if2), float(gravity)))
@@ -326,10 +331,12 @@ class LTSContext:
                 for i in range(k)}
 
 
-def _mesh_struct(mesh, use_positions=True, edge_weights=None):
+def _mesh_struct(mesh, use_positions=True, edge_weights=None, edge_signs=None):
     """ctypes lts_mesh of a mesh object (MPAS field names).  edge_weights:
     optional (n_edges_on_edge [nE], edges_on_edge [nE][maxE2],
-    weights_on_edge [nE][maxE2]) tables for the library to check."""
+    weights_on_edge [nE][maxE2]) tables for the library to check;
+    edge_signs: optional (edge_sign_on_cell [nC][maxE] or None,
+    edge_sign_on_vertex [nV][3] or None), int8, checked likewise."""
     i32 = lambda a: np.ascontiguousarray(a, np.int32)
     f64 = lambda a: np.ascontiguousarray(a, np.float64)
     arrs = dict(
@@ -350,6 +357,16 @@ def _mesh_struct(mesh, use_positions=True, edge_weights=None):
         assert ee.ndim == 2 and ee.shape == we.shape and ee.shape[0] == mesh.nEdges
         arrs.update(n_edges_on_edge=i32(ne), edges_on_edge=ee, weights_on_edge=we)
         m.max_edges2 = ee.shape[1]
+    if edge_signs is not None:
+        sc, sv = edge_signs
+        if sc is not None:
+            sc = np.ascontiguousarray(sc, np.int8)
+            assert sc.shape == (mesh.nCells, mesh.maxEdges)
+            arrs["edge_sign_on_cell"] = sc
+        if sv is not None:
+            sv = np.ascontiguousarray(sv, np.int8)
+            assert sv.shape == (mesh.nVertices, 3)
+            arrs["edge_sign_on_vertex"] = sv
     for k, v in arrs.items():
         setattr(m, k, _ptr(v))
     return m, arrs
@@ -359,7 +376,7 @@ PASS_NAMES = ["full", "step1", "step2", "step3", "step4"]
 
 
 def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = True,
-         edge_weights=None):
+         edge_weights=None, edge_signs=None):
     """Host-only lts_plan: labels, device ordering and pass ranges (no GPU)."""
     lib = load_library()
     if not hasattr(lib, "_plan_typed"):
@@ -368,7 +385,7 @@ def plan(mesh, fine_mask, n_if1: int = 2, n_if2: int = 2, use_positions: bool = 
             [ctypes.c_char_p, ctypes.c_int]
         lib.lts_plan.restype = ctypes.c_int
         lib._plan_typed = True
-    m, keep = _mesh_struct(mesh, use_positions, edge_weights)
+    m, keep = _mesh_struct(mesh, use_positions, edge_weights, edge_signs)
     fm = np.ascontiguousarray(fine_mask, np.uint8)
     out = dict(cell_region=np.empty(mesh.nCells, np.int8), edge_region=np.empty(mesh.nEdges, np.int8),
                cell_fbar=np.empty(mesh.nCells, np.uint8), edge_fbar=np.empty(mesh.nEdges, np.uint8),
@@ -605,6 +622,15 @@ class Surrogate:
         a = np.ascontiguousarray(p, np.float32)
         assert a.size == self.n_params
         self._check(self._lib.lts_sur_set_params(self._h, _ptr(a)))
+
+    def save(self, path):
+        """Shape, normalisation vector and parameters to a file (lts_sur_save)."""
+        self._check(self._lib.lts_sur_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Parameters (and the normalisation vector) from a file written by
+        save; the Adam state restarts."""
+        self._check(self._lib.lts_sur_load(self._h, os.fsencode(path)))
 
     def train(self, idx, lr: float = 1e-3):
         idx = np.ascontiguousarray(idx, np.int32)

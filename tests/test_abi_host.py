@@ -240,3 +240,33 @@ def test_mpas_weight_tables_checked_against_derived(lib, irregular):
     with pytest.raises(lts.LTSError) as ei:
         lts.plan(m, fm, 1, 1, edge_weights=(badn, ee, we))
     assert ei.value.status == lts.LTS_EMESH and "edge 9" in str(ei.value)
+
+
+def test_mpas_sign_tables_checked_against_orientation(lib, irregular):
+    """Optional edge_sign_on_cell / edge_sign_on_vertex tables that follow
+    the orientation convention (n_{e,i} = +1 for i = cells_on_edge[e][0],
+    t_{e,v} = +1 for v = vertices_on_edge[e][1]) pass; one flipped entry is
+    LTS_EMESH naming the cell or vertex."""
+    m = irregular
+    fm = (np.arange(m.nCells) % 16 < 5).astype(np.uint8)
+    sc = np.zeros((m.nCells, m.maxEdges), np.int8)
+    for i in range(m.nCells):
+        for j in range(m.nEdgesOnCell[i]):
+            e = m.edgesOnCell[i, j]
+            sc[i, j] = 1 if m.cellsOnEdge[e, 0] == i else -1
+    sv = np.where(m.verticesOnEdge[m.edgesOnVertex, 1] == np.arange(m.nVertices)[:, None],
+                  1, -1).astype(np.int8)
+    lts.plan(m, fm, 1, 1, edge_signs=(sc, sv))
+    bad = sc.copy()
+    bad[11, 1] = -bad[11, 1]
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm, 1, 1, edge_signs=(bad, None))
+    assert ei.value.status == lts.LTS_EMESH and "cell 11" in str(ei.value)
+    bad = sv.copy()
+    bad[23, 2] = -bad[23, 2]
+    with pytest.raises(lts.LTSError) as ei:
+        lts.plan(m, fm, 1, 1, edge_signs=(None, bad))
+    assert ei.value.status == lts.LTS_EMESH and "vertex 23" in str(ei.value)
+    # MPAS's opposite convention for cells is the negation: rejected as is
+    with pytest.raises(lts.LTSError):
+        lts.plan(m, fm, 1, 1, edge_signs=(-sc, None))

@@ -394,6 +394,37 @@ def test_surrogate_steps_conserve_mass(igw):
     assert d.n_nonfinite == 0 and abs(d.mass - m0) / m0 < 1e-13
 
 
+def test_save_and_load_round_trip(igw, tmp_path):
+    """lts_sur_save writes shape, normalisation and parameters; lts_sur_load
+    into a surrogate on another context restores them bitwise, so both
+    predict the same; a truncated file, a file of another kind and a missing
+    file are LTS_EINVAL and leave the loaded network as it was."""
+    w = igw
+    say("surrogate save / load", w.name)
+    a, b = _ctx(w), _ctx(w)
+    sa, sb = lts.Surrogate(a, seed=5), lts.Surrogate(b, seed=9)
+    sa.set_norm(np.array([0.1] * 5 + [1] * 7 + [1e-3, 2e-3, 0, 0], np.float32))
+    assert not np.array_equal(sa.get_params(), sb.get_params())
+    path = tmp_path / "net.bin"
+    sa.save(path)
+    sb.load(path)
+    assert np.array_equal(sa.get_params(), sb.get_params())
+    assert np.array_equal(sa.get_norm(), sb.get_norm())
+    pa, pb = sa.predict(), sb.predict()
+    assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
+    data = path.read_bytes()
+    (tmp_path / "short.bin").write_bytes(data[:-4])
+    (tmp_path / "long.bin").write_bytes(data + b"\0")
+    (tmp_path / "junk.bin").write_bytes(b"x" * len(data))
+    for bad in ("short.bin", "long.bin", "junk.bin", "missing.bin"):
+        with pytest.raises(lts.LTSError) as ei:
+            sb.load(tmp_path / bad)
+        assert ei.value.status == lts.LTS_EINVAL, bad
+    assert np.array_equal(sa.get_params(), sb.get_params())
+    for x in (sa, sb, a, b):
+        x.close()
+
+
 def test_timed_surrogate_step_matches_replayed_graph(igw):
     """In the context's timing mode a surrogate step is launched pass by pass
     with event stamps instead of replaying its graph: the same states and gate

@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload",
-                    choices=["vr", "igw", "sphere", "ensemble", "surrogate", "gemm"],
+                    choices=["vr", "vr3", "igw", "sphere", "ensemble", "surrogate", "gemm"],
                     default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline LTS3 run (the other one is a comparison)")
@@ -249,10 +249,20 @@ def main():
                          "RK4 and SSPRK3 at their largest stable steps")
     ap.add_argument("--max-dt-hours", type=float, default=1.0,
                     help="simulated time of every run of the maximum-time-step test")
+    ap.add_argument("--levels", action="store_true",
+                    help="three LTS levels (Remark 3.1) against the two-level step on the "
+                         "workload: level 1 = cells whose target spacing is below "
+                         "--level-spacing times the finest, ratios (M/2, 2) against M")
+    ap.add_argument("--level-spacing", type=float, default=None,
+                    help="--levels: target-spacing threshold of the inner fine level "
+                         "(default: the workload's own inner level, else 2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    args.level_spacing_default = args.level_spacing is None
+    if args.level_spacing is None:
+        args.level_spacing = 2.0
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the sharded design is documented, not built); run with --gpus 1",
@@ -286,6 +296,8 @@ def main():
     t0 = time.time()
     if args.workload == "sphere":
         w = workloads.sphere_cap(case=args.case)
+    elif args.workload == "vr3":
+        w = workloads.vr3_planar()
     else:
         w = workloads.vr_planar() if args.workload == "vr" else workloads.igw_hex()
     m = w.mesh
@@ -318,6 +330,10 @@ def main():
         if L > 1:
             sys.exit("--max-dt runs on one layer")
         return bench_max_dt(args, w, make, lts, torch, stream, prec, h0, u0)
+    if args.levels:
+        if L > 1 or args.workload == "igw":
+            sys.exit("--levels runs on one layer of the vr or sphere workload")
+        return bench_levels(args, w, lts, torch, stream, prec)
 
     # ------------------------------------------------------------ timed region
     ctx = make(prec)
@@ -518,6 +534,112 @@ def main():
                           "sample": f"{n_one} coarse steps in {t_one:.1f}s, one thread, "
                                     f"same build"}}
     log(f"cpu baseline: {out['cpu_baseline']}")
+    emit(out)
+
+
+def bench_levels(args, w, lts, torch, stream, prec):
+    """More than two LTS levels (Remark 3.1) against the two-level step on the
+    same workload and coarse step: level 0's fine region as in the two-level
+    run, level 1 the cells whose target spacing is below `--level-spacing`
+    times the finest, step ratios (M/2, 2) against M.  Level 0's cells outside
+    level 1 then step at 2 dt / M, which their spacing (at least that factor
+    above the smallest) keeps within the fine step's Courant number.  Both
+    run the same simulated time (`--sim-hours`); errors against FP64 SSPRK3
+    at a quarter of the fine step; cell-tendency evaluations per coarse step
+    counted from the region labels."""
+    import numpy as np
+    m, M, dt = w.mesh, w.M, w.dt_coarse
+    if M % 2:
+        sys.exit("--levels needs an even M")
+    if w.extra.get("level1_mask") is not None and args.level_spacing_default:
+        fm1 = (w.extra["level1_mask"] & w.fine_mask).astype(np.uint8)
+    else:
+        if w.name.startswith("sphere"):
+            from paper_2106_07154_amd.inputs import voronoi_sphere as vs
+            xc = np.stack([m.xCell, m.yCell, m.zCell], 1) / vs.EARTH_RADIUS
+            shape = vs.cap_spacing_shape(xc)
+        else:
+            from paper_2106_07154_amd.inputs import voronoi_planar as vp
+            shape = (vp.vr3_spacing_shape if w.name.startswith("vr3") else
+                     vp.vr_spacing_shape)(m.xCell, m.yCell)
+        fm1 = ((shape < args.level_spacing) & (w.fine_mask != 0)).astype(np.uint8)
+    Ms = (M // 2, 2)
+    sp = stream.cuda_stream
+    T = args.sim_hours * 3600.0
+    n = max(1, int(round(T / dt)))
+    dtc = T / n
+
+    def ctx(levels):
+        c = lts.LTSContext(0, prec, stream=sp)
+        if levels:
+            c.upload_mesh_levels(m, [w.fine_mask, fm1], w.n_if1, w.n_if2, w.gravity)
+        else:
+            c.upload_mesh(m, w.fine_mask, w.n_if1, w.n_if2, w.gravity)
+        c.init_state(w.h0, w.u0)
+        return c
+
+    ref = lts.LTSContext(0, "fp64", stream=sp)
+    ref.upload_mesh(m, w.fine_mask, w.n_if1, w.n_if2, w.gravity)
+    ref.init_state(w.h0, w.u0)
+    ref.step_rk3(dtc / (4 * M), n * 4 * M)
+    h_ref, _ = ref.get_state()
+    ref.close()
+    H = float(np.median(w.h0))
+    err = lambda h: rel_l2(h - H, h_ref - H, m.areaCell) if np.all(np.isfinite(h)) else None
+
+    # cell-tendency evaluations per coarse step from the labels.  Two levels
+    # (Algorithm 2.2): 3|C| + (2 + 3M)|I| + 3M|F| + |F̲|.  Three levels (the
+    # reading of Remark 3.1): level 0's Steps 1, 2 and 4, then M_0 level-1
+    # LTS3 steps on F_0, each evaluating level 1's coarse part inside F_0 and
+    # level 0's interface (whose accumulation they supply) three times, level
+    # 1's interface 2 + 3 M_1 times, its fine region 3 M_1 times and its
+    # underlined F once more.
+    two = ctx(False)
+    three = ctx(True)
+
+    def evals(levels):
+        if not levels:
+            r, _, fb, _ = two.regions()
+            C, I, F = (r == 0).sum(), ((r == 1) | (r == 2)).sum(), (r == 3).sum()
+            return int(3 * C + (2 + 3 * M) * I + 3 * M * F + (fb != 0).sum())
+        r0, _, f0, _ = three.level_regions(0)
+        r1, _, f1, _ = three.level_regions(1)
+        C0, I0 = (r0 == 0).sum(), ((r0 == 1) | (r0 == 2)).sum()
+        C1 = ((r1 == 0) & (r0 == 3)).sum()
+        I1, F1 = ((r1 == 1) | (r1 == 2)).sum(), (r1 == 3).sum()
+        sub = 3 * C1 + 3 * I0 + (2 + 3 * Ms[1]) * I1 + 3 * Ms[1] * F1 + (f1 != 0).sum()
+        return int(3 * C0 + 2 * I0 + (f0 != 0).sum() + Ms[0] * sub)
+
+    runs = {}
+    for name, c, go in (("two_level", two, lambda k: two.step(dtc, M, k)),
+                        ("three_level", three, lambda k: three.step_levels(dtc, Ms, k))):
+        go(2)
+        c.init_state(w.h0, w.u0)
+        try:
+            ms = timed(torch, stream, lambda: go(n))
+            h, _ = c.get_state()
+            runs[name] = {"ms": round(ms, 3), "ms_per_step": round(ms / n, 4), "err": err(h),
+                          "cell_evals_per_step": evals(name == "three_level")}
+        except lts.LTSError as ex:
+            runs[name] = {"ms": None, "err": None, "diverged": str(ex)}
+        log(f"{name}: {runs[name]}")
+        c.close()
+    a, b = runs["two_level"], runs["three_level"]
+    value = m.nCells * M * n / (b["ms"] / 1e3) if b.get("ms") else None
+    out = {"metric": "cell-updates/s of three-level LTS3 (Remark 3.1) against the two-level step",
+           "value": round(value, 1) if value else None, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": n, "warmup": 2, "ms_per_step": b.get("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": f"{w.name}-levels", "cells": m.nCells, "M": M, "Ms": list(Ms),
+                      "level1_cells": int(fm1.sum()), "level0_fine_cells": int(w.fine_mask.sum()),
+                      "level_spacing": None if args.level_spacing_default and
+                      w.extra.get("level1_mask") is not None else args.level_spacing,
+                      "sim_hours": args.sim_hours},
+           "runs": runs,
+           "three_over_two_level_time": round(a["ms"] / b["ms"], 3) if a.get("ms") and b.get("ms") else None,
+           "work_ratio_two_over_three": round(a["cell_evals_per_step"] / b["cell_evals_per_step"], 3)
+           if a.get("cell_evals_per_step") and b.get("cell_evals_per_step") else None}
     emit(out)
 
 

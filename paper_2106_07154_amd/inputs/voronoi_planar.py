@@ -325,6 +325,33 @@ def vr_points(n: int, seed: int, iters: int, progress=None):
     return p
 
 
+# A three-resolution variant (more than two LTS levels, Remark 3.1): spacing 1
+# inside a 60 km disk, 2 in a ring out to 300 km, 8 outside.
+VR3_R1, VR3_W1 = 6.0e4, 1.5e4
+VR3_R2, VR3_W2 = 3.0e5, 5.0e4
+VR3_MID = 2.0
+
+
+def vr3_spacing_shape(x, y):
+    """Relative target spacing of the three-resolution workload (1, 2, 8 with
+    tanh blends of 15 and 50 km)."""
+    d = np.hypot(x - VR_DOMAIN / 2, y - VR_DOMAIN / 2)
+    return (1.0 + (VR3_MID - 1.0) * 0.5 * (1.0 + np.tanh((d - VR3_R1) / VR3_W1)) +
+            (VR_RATIO - VR3_MID) * 0.5 * (1.0 + np.tanh((d - VR3_R2) / VR3_W2)))
+
+
+def vr3_points(n: int, seed: int, iters: int, progress=None):
+    """Seeded points Lloyd-relaxed under rho ~ spacing^-4 (three resolutions)."""
+    L = VR_DOMAIN
+    p = sample_points(n, L, L, vr3_spacing_shape, seed)
+    dens = lambda x, y: vr3_spacing_shape(x, y) ** -4.0
+    for it in range(iters):
+        p = lloyd_step(p, L, L, dens)
+        if progress:
+            progress(it)
+    return p
+
+
 def morton_sort(points, L):
     q = np.clip((points / L * 65535.0).astype(np.int64), 0, 65535)
 

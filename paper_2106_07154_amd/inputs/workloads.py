@@ -93,6 +93,51 @@ def vr_planar(n=VR_N, seed=VR_SEED, iters=VR_ITERS, H=500.0, amp=5.0, sigma=4.0e
 
 
 # ---------------------------------------------------------------------------
+# Three resolutions (800k cells): the multi-level LTS3 workload
+
+VR3_SEED = 2106071542
+VR3_N = 800_000
+VR3_ITERS = 30
+
+
+def _vr3_cache_path(n, seed, iters):
+    return os.path.join(DATA, f"vr3_{n}_s{seed}_i{iters}_u32.npy")
+
+
+def vr3_points_cached(n=VR3_N, seed=VR3_SEED, iters=VR3_ITERS, progress=None):
+    path = _vr3_cache_path(n, seed, iters)
+    L = vp.VR_DOMAIN
+    if os.path.exists(path):
+        q = np.load(path, allow_pickle=False)
+        return q.astype(np.float64) * (L / 2.0 ** 32)
+    p = vp.morton_sort(vp.vr3_points(n, seed, iters, progress), L)
+    return quantize(p, L).astype(np.float64) * (L / 2.0 ** 32)
+
+
+def vr3_planar(n=VR3_N, seed=VR3_SEED, iters=VR3_ITERS, H=500.0, amp=5.0, sigma=4.0e4,
+               M=8, progress=None) -> Workload:
+    """Three resolutions in the 2000 km periodic domain: target spacing 1
+    inside a 60 km disk, 2 in a ring to 300 km, 8 outside (tanh blends of 15
+    and 50 km); Gaussian bump over H = 500 m at rest; fine region (level 0):
+    target spacing below 0.9 of the outer one; `extra["level1_mask"]`: target
+    spacing below 1.5 (the disk, for an inner level with ratio 2); fine step
+    0.3 of the gravity-wave crossing time of the smallest cell."""
+    L = vp.VR_DOMAIN
+    pts = vr3_points_cached(n, seed, iters, progress)
+    m = vp.periodic_voronoi_mesh(pts, L, L, f0=1.0e-4, name=f"vr3-{n}")
+    shape = vp.vr3_spacing_shape(m.xCell, m.yCell)
+    fm = (shape < 0.9 * vp.VR_RATIO).astype(np.uint8)
+    h0, u0 = gaussian_bump_state(m, H, amp, sigma, L / 2, L / 2)
+    c = math.sqrt(9.81 * H)
+    spacing = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
+    dt_fine = 0.3 * spacing.min() / c
+    return Workload(f"vr3-planar-{n // 1000}k", m, fm, h0, u0, dt_fine * M, M,
+                    extra=dict(dt_fine=dt_fine, spacing_min=float(spacing.min()),
+                               spacing_max=float(spacing.max()), H=H,
+                               level1_mask=(shape < 1.5).astype(np.uint8)))
+
+
+# ---------------------------------------------------------------------------
 # The batched ensemble: 64 members of 10k-400k cells (log-uniform, seeded)
 
 ENS_SEED = 7000

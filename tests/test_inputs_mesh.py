@@ -110,3 +110,21 @@ def test_sphere_invariants(sphere_mesh):
     s = vs.cap_spacing_shape(xc / vs.EARTH_RADIUS)
     a_in, a_out = m.areaCell[s < 1.2].mean(), m.areaCell[s > 3.8].mean()
     assert 8.0 < a_out / a_in < 24.0
+
+
+def test_three_resolution_generator():
+    """The three-resolution family (the multi-level workload's generator, at
+    12,000 points): a valid Voronoi mesh whose median cell spacing in the
+    disk, the ring and outside follows the target 1 : 2 : 8 to within 25 %."""
+    from paper_2106_07154_amd.inputs import voronoi_planar as vp
+    L = vp.VR_DOMAIN
+    p = vp.vr3_points(12000, 7, 12)
+    m = periodic_voronoi_mesh(p, L, L, f0=1e-4, name="vr3-small")
+    _voronoi_invariants(m)
+    d = np.hypot(m.xCell - L / 2, m.yCell - L / 2)
+    sp = np.sqrt(m.areaCell / (math.sqrt(3.0) / 2.0))
+    s_in = np.median(sp[d < 0.6 * vp.VR3_R1])
+    s_ring = np.median(sp[(d > vp.VR3_R1 + 3 * vp.VR3_W1) & (d < vp.VR3_R2 - 2 * vp.VR3_W2)])
+    s_out = np.median(sp[d > vp.VR3_R2 + 4 * vp.VR3_W2])
+    assert abs(s_ring / s_in / 2.0 - 1.0) < 0.25, (s_in, s_ring)
+    assert abs(s_out / s_in / 8.0 - 1.0) < 0.25, (s_in, s_out)

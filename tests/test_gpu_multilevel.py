@@ -206,3 +206,34 @@ def test_level_errors(strips):
         c.step_levels(60.0, (2, 0), 1)
     assert ei.value.status == lts.LTS_EINVAL
     c.close()
+
+
+def test_multilevel_parity_vr3_full_size():
+    """The benchmark's three-level configuration at full size
+    (vr3-planar-800k, ratios (4, 2), level 1 the 61k-cell disk inside the
+    410k-cell level-0 region): labels bit-exact, and two coarse steps from a
+    state with flow against the oracle's multi-level step at the two-level
+    full-size tolerances (h 1e-12, u 1e-11, the perturbation h - H 1e-9)."""
+    import os
+    from paper_2106_07154_amd.inputs import workloads as wl
+    w = wl.vr3_planar()
+    m = w.mesh
+    masks = [w.fine_mask, (w.extra["level1_mask"] & w.fine_mask).astype(np.uint8)]
+    say("multilevel vr3 full size", m.nCells)
+    o = Oracle(m, w.gravity, threads=min(16, os.cpu_count() or 1))
+    R = o.ml_regions(masks, 2, 2)
+    h, u = o.ssprk(w.h0, w.u0, w.dt_coarse / w.M, n=8)
+    c = lts.LTSContext(0, "fp64")
+    c.upload_mesh_levels(m, masks, 2, 2, w.gravity)
+    for l in range(2):
+        cr, er, cf, ef = c.level_regions(l)
+        assert np.array_equal(cr, R.cell[l]) and np.array_equal(er, R.edge[l])
+    c.init_state(h, u)
+    c.step_levels(w.dt_coarse, (4, 2), 2)
+    gh, gu = c.get_state()
+    c.close()
+    rh, ru = o.mlts(h, u, w.dt_coarse, [4, 2], R, n=2)
+    eh, eu = rel_l2(gh, rh, m.areaCell), rel_l2(gu, ru, m.dvEdge * m.dcEdge)
+    ep = rel_l2(gh - 500.0, rh - 500.0, m.areaCell)
+    say("rel L2 h u h-H", eh, eu, ep)
+    assert eh < 1e-12 and eu < 1e-11 and ep < 1e-9

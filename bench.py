@@ -624,6 +624,30 @@ def bench_levels(args, w, lts, torch, stream, prec):
             runs[name] = {"ms": None, "err": None, "diverged": str(ex)}
         log(f"{name}: {runs[name]}")
         c.close()
+    # at equal error: each form at coarse steps 1-2x the operating one over
+    # the same simulated time; the fastest run within eps = 2x the two-level
+    # error at the operating step counts
+    tts = {"two_level": [], "three_level": []}
+    eps = 2.0 * runs["two_level"]["err"] if runs["two_level"].get("err") else None
+    for f in (1.0, 1.25, 4.0 / 3.0, 1.6, 2.0):
+        nf = max(1, int(round(T / (dt * f))))
+        for name, lev in (("two_level", False), ("three_level", True)):
+            c = ctx(lev)
+            go = (lambda k: c.step_levels(T / nf, Ms, k)) if lev else (lambda k: c.step(T / nf, M, k))
+            try:
+                go(1)
+                c.init_state(w.h0, w.u0)
+                ms = timed(torch, stream, lambda: go(nf))
+                h, _ = c.get_state()
+                tts[name].append({"step_factor": round(f, 4), "steps": nf, "ms": round(ms, 3),
+                                  "err": err(h)})
+            except lts.LTSError:
+                tts[name].append({"step_factor": round(f, 4), "steps": nf, "ms": None,
+                                  "err": None})
+            c.close()
+    best = {k: min([r["ms"] for r in v if r["ms"] and r["err"] is not None and eps and
+                    r["err"] <= eps], default=None) for k, v in tts.items()}
+    log(f"time to solution (eps {eps}): {json.dumps(tts)}")
     a, b = runs["two_level"], runs["three_level"]
     value = m.nCells * M * n / (b["ms"] / 1e3) if b.get("ms") else None
     out = {"metric": "cell-updates/s of three-level LTS3 (Remark 3.1) against the two-level step",
@@ -639,7 +663,10 @@ def bench_levels(args, w, lts, torch, stream, prec):
            "runs": runs,
            "three_over_two_level_time": round(a["ms"] / b["ms"], 3) if a.get("ms") and b.get("ms") else None,
            "work_ratio_two_over_three": round(a["cell_evals_per_step"] / b["cell_evals_per_step"], 3)
-           if a.get("cell_evals_per_step") and b.get("cell_evals_per_step") else None}
+           if a.get("cell_evals_per_step") and b.get("cell_evals_per_step") else None,
+           "time_to_solution": {"eps": eps, "runs": tts, "best_ms": best,
+                                "two_over_three": round(best["two_level"] / best["three_level"], 3)
+                                if best["two_level"] and best["three_level"] else None}}
     emit(out)
 
 

@@ -121,11 +121,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES):
+    """Hash of the sources' code with comments and runs of blank space
+    removed, so a recorded counter figure survives comment-only edits and is
+    dropped by any change to the code itself."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sources:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            txt = fh.read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(re.sub(r"\s+", " ", txt).strip().encode())
     return h.hexdigest()[:16]
 
 

@@ -19,11 +19,12 @@ constexpr bool perturbation_form() {
 // Device mesh, permuted so that every LTS region is a contiguous range.
 // Per-cell slot tables are compact: the n_i slots of cell i (counter-
 // clockwise) are entries cso[i].x .. cso[i].x + n_i - 1, cells one after
-// another in device order, no padding.  The cell kernel gives each slot its
-// own lane (G = padded_slots(maxE) lanes per cell); lanes past n_i re-read
-// the cell's last entry (a cache line already fetched) and zero its
-// coefficients in registers.  A wavefront's table reads are one contiguous
-// run of about 6 entries per cell.
+// another in device order, no padding.  The cell kernels give each slot its
+// own lane: 8 lanes per cell in the single-range kernel (cells with more
+// than 8 edges take appended 16-lane blocks), G = padded_slots(maxE) in the
+// batched kernel; lanes past n_i re-read the cell's last entry (a cache line
+// already fetched) and zero its coefficients in registers.  A wavefront's
+// table reads are one contiguous run of about 6 entries per cell.
 template <typename T>
 struct DevMesh {
     int nC, nE, nV, maxE;  // maxE: largest n_i of the mesh

@@ -269,7 +269,7 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     c.o = (size_t)so.x + min(lane, so.y - 1);
     c.i = i;
     c.lane = lane;
-    c.live = live && so.y <= G;  // wider cells: the 16-lane list kernel
+    c.live = live && so.y <= G;  // wider cells: the appended 16-lane blocks
     c.e = m.eoc[c.o];
     const int nb = m.coc[c.o];
     c.nl = lane < so.y ? m.nl[c.o] : T(0);

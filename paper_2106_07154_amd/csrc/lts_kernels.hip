@@ -437,8 +437,28 @@ __global__ __launch_bounds__(kBlock) void k_edge(const T* __restrict__ zs, int n
 // ---------------------------------------------------------------------------
 // Batched (ensemble) kernels.  A launch carries a work list: item k covers
 // virtual blocks [first_k, first_k + nblk_k + nblk_aux_k) of one member's
-// range.  The grid is persistent (fixed size, chosen by the autotuner) and
-// strides over the virtual blocks; each block finds its item by binary search.
+// range.  The grid is persistent (fixed size, chosen by the autotuner); each
+// block finds its item by binary search.
+//
+// Virtual blocks [0, nvb) are split into one contiguous chunk per XCD, sized
+// by the XCD's share of the grid (blocks are dispatched round-robin over the
+// 8 XCDs), and the XCD's blocks stride over its chunk, so neighbouring cells'
+// gathers meet in one L2 (with a plain grid stride every line shared by
+// adjacent virtual blocks is fetched into several L2s).  Every virtual block
+// is visited once whatever the placement.
+struct VbRange {
+    int vb, end, step;
+};
+__device__ __forceinline__ VbRange xcd_range(int nvb) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+    const int before = x * q + min(x, r);  // blocks on the XCDs before x
+    const int mine = q + (x < r ? 1 : 0);  // blocks on XCD x (k < mine)
+    const int lo = (int)((long long)nvb * before / nb);
+    const int hi = (int)((long long)nvb * (before + mine) / nb);
+    return VbRange{lo + k, hi, mine};
+}
+
 template <typename T>
 __device__ __forceinline__ int find_item(const Item<T>* items, int nitems, int vb) {
     int lo = 0, hi = nitems - 1;
@@ -453,7 +473,8 @@ __device__ __forceinline__ int find_item(const Item<T>* items, int nitems, int v
 template <typename T>
 __global__ __launch_bounds__(512) void kb_vertex(const Item<T>* __restrict__ items, int nitems,
                                                  int nvb) {
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    for (VbRange r = xcd_range(nvb); r.vb < r.end; r.vb += r.step) {
+        const int vb = r.vb;
         const Item<T>& w = items[find_item(items, nitems, vb)];
         const int v = w.lo + (vb - w.first) * (int)blockDim.x + threadIdx.x;
         if (v < w.hi) vertex_body<T, perturbation_form<T>()>(w.m, w.h, w.u, w.q, v);
@@ -466,7 +487,8 @@ __global__ __launch_bounds__(512) void kb_vertex(const Item<T>* __restrict__ ite
 template <typename T, int G>
 __global__ __launch_bounds__(512) void kb_cell(const Item<T>* __restrict__ items, int nitems,
                                                int nvb) {
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    for (VbRange r = xcd_range(nvb); r.vb < r.end; r.vb += r.step) {
+        const int vb = r.vb;
         const Item<T>& w = items[find_item(items, nitems, vb)];
         cell_body<T, G, perturbation_form<T>(), false>(w.m, w.h, w.u, w.q, w.zs,
                                (vb - w.first) * (int)blockDim.x + threadIdx.x, w.lo, w.hi, w.g,
@@ -477,7 +499,8 @@ __global__ __launch_bounds__(512) void kb_cell(const Item<T>* __restrict__ items
 template <typename T>
 __global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items, int nitems,
                                                int nvb) {
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    for (VbRange r = xcd_range(nvb); r.vb < r.end; r.vb += r.step) {
+        const int vb = r.vb;
         const Item<T>& w = items[find_item(items, nitems, vb)];
         const int k = vb - w.first;
         if (k < w.nblk) {

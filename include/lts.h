@@ -155,8 +155,8 @@ lts_status lts_upload_mesh(lts_ctx *ctx, const lts_mesh *mesh, const uint8_t *fi
    interface-2 cell of level l >= 1 must lie at least four cell rings inside
    F_{l-1} (LTS_ELABEL otherwise: three rings are what the method needs, the
    fourth keeps every level's evaluation sets contiguous in device order).
-   n_fine_levels = 1 is lts_upload_mesh; more than one needs a single-layer
-   context.  Level 0's labels are the ones lts_get_regions and
+   n_fine_levels = 1 is lts_upload_mesh.  Layered contexts (lts_set_layers)
+   advance every layer through the same levels.  Level 0's labels are the ones lts_get_regions and
    lts_region_counts report, and lts_step runs the two-level scheme on them. */
 lts_status lts_upload_mesh_levels(lts_ctx *ctx, const lts_mesh *mesh, int n_fine_levels,
                                   const uint8_t *fine_masks, int n_if1_rings, int n_if2_rings,

@@ -1050,8 +1050,6 @@ lts_status lts_upload_mesh_levels(lts_ctx* c, const lts_mesh* m, int nfine, cons
     if (!c || !m || !fine) return c ? fail(c, LTS_EINVAL, "NULL argument") : LTS_EINVAL;
     if (nfine < 1 || nfine > LTS_MAX_LEVELS - 1)
         return fail(c, LTS_EINVAL, "n_fine_levels must be 1 .. LTS_MAX_LEVELS - 1");
-    if (nfine > 1 && c->L != 1)
-        return fail(c, LTS_EINVAL, "more than one fine level needs a single-layer context");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LTS_EDEVICE, "hipSetDevice");
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_device(c);

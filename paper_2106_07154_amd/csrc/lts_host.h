@@ -212,8 +212,7 @@ struct Run {
         return pass_plan(c->plan[p], h, u, cs0, cs1, es0, es1, aux);
     }
 
-    // The same with an explicit plan and up to two appended element-wise jobs
-    // (aux2: single-layer contexts only).
+    // The same with an explicit plan and up to two appended element-wise jobs.
     lts_status pass_plan(const PassPlan& P, const T* h, const T* u, const Seg<T>& cs0,
                          const Seg<T>& cs1, const Seg<T>& es0, const Seg<T>& es1,
                          const Aux<T>& aux, const Aux<T>& aux2 = Aux<T>()) {
@@ -232,7 +231,7 @@ struct Run {
             done(KC_CELL, e0, e1, kernel_bytes<T>(P, KC_CELL, cs0, cs1, aux, L));
             if ((st = events(&e0, &e1))) return st;
             HIPCHK(c, launch_edge_l<T>(zs, c->nE, P.et_lo, P.et_hi, L, es0, es1, aux, c->flag, s,
-                                       e0, e1));
+                                       e0, e1, aux2));
             done(KC_EDGE, e0, e1, kernel_bytes<T>(P, KC_EDGE, es0, es1, aux, L));
             return LTS_OK;
         }
@@ -315,10 +314,10 @@ struct Run {
         double cf[3];
         predict_coeffs(stage, k, M, cf, 3);
         x.kind = 1;
-        x.nh = V.cb[4] - V.cb[3];
-        x.nu = V.eb[3] - V.eb[2];
-        x.lo_h = V.cb[3];
-        x.lo_u = V.eb[2];
+        x.nh = (V.cb[4] - V.cb[3]) * c->L;  // flat element x layer units
+        x.nu = (V.eb[3] - V.eb[2]) * c->L;
+        x.lo_h = V.cb[3] * c->L;
+        x.lo_u = V.eb[2] * c->L;
         x.xh = xh;
         x.xu = xu;
         x.ah = (T*)V.x0h; x.bh = (T*)V.x1h; x.ch = (T*)V.x2h;
@@ -330,12 +329,12 @@ struct Run {
         const LevelData& V = c->lv[l];
         Aux<T> x;
         x.kind = 2;
-        x.nh = V.cb[5] - V.cb[3];
-        x.nu = V.eb[4] - V.eb[2];
-        x.nbh = V.cb[4] - V.cb[3];
-        x.nbu = V.eb[3] - V.eb[2];
-        x.lo_h = V.cb[3];
-        x.lo_u = V.eb[2];
+        x.nh = (V.cb[5] - V.cb[3]) * c->L;  // flat element x layer units
+        x.nu = (V.eb[4] - V.eb[2]) * c->L;
+        x.nbh = (V.cb[4] - V.cb[3]) * c->L;
+        x.nbu = (V.eb[3] - V.eb[2]) * c->L;
+        x.lo_h = V.cb[3] * c->L;
+        x.lo_u = V.eb[2] * c->L;
         x.xh = (T*)c->Ah;
         x.xu = (T*)c->Au;
         x.ah = (T*)V.x0h; x.bh = (T*)V.acch;

@@ -202,7 +202,8 @@ hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q
 template <typename T>
 hipError_t launch_edge_l(const T* zs, int nE, int lo, int hi, int L, const Seg<T>& s0,
                          const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
-                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                         const Aux<T>& aux2 = Aux<T>());
 int diag_blocks(int n);
 hipError_t launch_fill_int(int* p, int v, hipStream_t s);
 

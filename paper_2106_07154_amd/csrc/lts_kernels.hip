@@ -953,9 +953,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_l(DevMesh<T> m, const T* __rest
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_edge_l(const T* __restrict__ zs, int nE, int lo,
                                                    int hi, int L, int nbe, Seg<T> s0, Seg<T> s1,
-                                                   Aux<T> aux, int* flag) {
+                                                   Aux<T> aux, int nba, Aux<T> aux2, int* flag) {
     if ((int)blockIdx.x >= nbe) {
-        run_aux(aux, (blockIdx.x - nbe) * kBlock + threadIdx.x);
+        const int b = blockIdx.x - nbe;
+        if (b < nba) run_aux(aux, b * kBlock + threadIdx.x);
+        else run_aux(aux2, (b - nba) * kBlock + threadIdx.x);
         return;
     }
     const int b = blockIdx.x, x = b & 7, k = b >> 3, qq = nbe >> 3, r = nbe & 7;
@@ -1074,12 +1076,13 @@ hipError_t launch_cell_l(const DevMesh<T>& m, const T* h, const T* u, const T* q
 template <typename T>
 hipError_t launch_edge_l(const T* zs, int nE, int lo, int hi, int L, const Seg<T>& s0,
                          const Seg<T>& s1, const Aux<T>& aux, int* flag, hipStream_t s,
-                         hipEvent_t ev0, hipEvent_t ev1) {
+                         hipEvent_t ev0, hipEvent_t ev1, const Aux<T>& aux2) {
     const int nbe = hi > lo ? (int)nblocks((long)(hi - lo) * L) : 0;
     const int nba = aux.kind ? (int)nblocks((long)aux.nh + aux.nu) : 0;
-    if (nbe + nba == 0) return hipSuccess;
-    return launch(k_edge_l<T>, dim3(nbe + nba), s, ev0, ev1, zs, nE, lo, hi, L, nbe, s0, s1, aux,
-                  flag);
+    const int nba2 = aux2.kind ? (int)nblocks((long)aux2.nh + aux2.nu) : 0;
+    if (nbe + nba + nba2 == 0) return hipSuccess;
+    return launch(k_edge_l<T>, dim3(nbe + nba + nba2), s, ev0, ev1, zs, nE, lo, hi, L, nbe, s0, s1,
+                  aux, nba, aux2, flag);
 }
 
 template <typename T>
@@ -1172,7 +1175,7 @@ hipError_t launch_fill_int(int* p, int v, hipStream_t s) {
                                          hipStream_t, hipEvent_t, hipEvent_t);                   \
     template hipError_t launch_edge_l<T>(const T*, int, int, int, int, const Seg<T>&,            \
                                          const Seg<T>&, const Aux<T>&, int*, hipStream_t,        \
-                                         hipEvent_t, hipEvent_t);
+                                         hipEvent_t, hipEvent_t, const Aux<T>&);
 
 LTS_INSTANTIATE(double)
 LTS_INSTANTIATE(float)

@@ -237,3 +237,40 @@ def test_multilevel_parity_vr3_full_size():
     ep = rel_l2(gh - 500.0, rh - 500.0, m.areaCell)
     say("rel L2 h u h-H", eh, eu, ep)
     assert eh < 1e-12 and eu < 1e-11 and ep < 1e-9
+
+
+@pytest.mark.parametrize("L,prec", [(3, "fp64"), (3, "fp32"), (64, "fp64")])
+def test_multilevel_layers_parity(disks, L, prec):
+    """Multi-level LTS3 on a layered context: L independent layers with
+    different states, each against the oracle's multi-level step on that
+    layer alone (3 layers: one thread per (element, layer); 64: one wave per
+    element), at the single-layer tolerances; the mass of all layers is
+    conserved to 1e-13 in FP64."""
+    m, h0, u0, masks = disks
+    say("multilevel layers", L, prec)
+    rng = np.random.default_rng(70 + L)
+    hs = np.array([h0 + 0.2 * (l % 5) * rng.standard_normal(m.nCells) for l in range(L)])
+    us = np.array([u0 * (1.0 + 0.1 * (l % 7)) for l in range(L)])
+    Ms, dt, n = (2, 3), 40.0, 4
+    c = lts.LTSContext(0, prec, layers=L)
+    c.upload_mesh_levels(m, masks, 2, 2)
+    c.init_state(hs, us)
+    m0 = c.diagnostics().mass
+    c.step_levels(dt, Ms, n)
+    gh, gu = c.get_state()
+    d = c.diagnostics()
+    c.close()
+    o = Oracle(m)
+    R = o.ml_regions(masks, 2, 2)
+    tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
+    worst = (0.0, 0.0)
+    for l in range(L):
+        rh, ru = o.mlts(hs[l], us[l], dt, list(Ms), R, n=n)
+        eh, eu = rel_l2(gh[l], rh, m.areaCell), rel_l2(gu[l], ru, m.dvEdge * m.dcEdge)
+        worst = (max(worst[0], eh), max(worst[1], eu))
+        assert eh < tol_h and eu < tol_u, (l, eh, eu)
+    say("worst rel L2 h u over layers", *worst)
+    assert d.n_nonfinite == 0
+    if prec == "fp64":
+        say("mass drift", abs(d.mass - m0) / m0)
+        assert abs(d.mass - m0) / m0 < 1e-13

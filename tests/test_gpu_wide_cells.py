@@ -196,3 +196,55 @@ def test_declared_capacity_is_not_the_lane_count(hex16, prec):
     rh, ru = o.lts(h0, u0, 30.0, 4, o.regions(fm, 2, 2), n=6)
     tol_h, tol_u = (1e-12, 1e-11) if prec == "fp64" else (1e-5, 1e-5)
     assert rel_l2(out[1][0], rh) < tol_h and rel_l2(out[1][1], ru) < tol_u
+
+
+@pytest.fixture(scope="module")
+def wide_levels():
+    """A 32 x 32 ring lattice (10 km, one 11-gon at the centre) with nested
+    fine disks placing the 11-gon in the inner fine region, the inner first
+    interface ring, the inner coarse region (fine at level 0) or the outer
+    first interface ring."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07154_amd.inputs.voronoi_planar import periodic_voronoi_mesh, ring_hex_points
+    p, Lx, Ly = ring_hex_points(32, 32, 1.0e4, 11, 1.2, 30)
+    m = periodic_voronoi_mesh(p, Lx, Ly, f0=1.0e-4, name="ring11-32")
+    assert m.nEdgesOnCell.max() == 11
+    rng = np.random.default_rng(14)
+    m.bottom = 20.0 * rng.standard_normal(m.nCells)
+    c11 = int(np.argmax(m.nEdgesOnCell))
+    x0, y0 = m.xCell[c11], m.yCell[c11]
+    d = lambda cx, r: disk_fine_mask(m, cx % Lx, y0, r)
+    cases = {"inner_f": ([d(x0, 1.2e5), d(x0, 2.5e4)], (3, 3)),
+             "inner_i1": ([d(x0, 1.3e5), d(x0 + 3.5e4, 2.0e4)], (3, 2)),
+             "inner_c": ([d(x0 + 5e4, 1.25e5), d(x0 + 8e4, 2.0e4)], (3, 0)),
+             "outer_i1": ([d(x0 + 1.05e5, 1.0e5), d(x0 + 1.1e5, 2.0e4)], (2, 0))}
+    o = Oracle(m)
+    for name, (masks, want) in cases.items():
+        R = o.ml_regions(masks, 2, 2)
+        assert (R.cell[0][c11], R.cell[1][c11]) == want, name
+        lts.plan_levels(m, masks, 2, 2)  # the library's nesting rule (four rings) holds too
+    h, u = gaussian_bump_state(m, 500.0, 5.0, 2.0e4, x0 + 5e3, y0 - 3e3)
+    h2, u2 = random_state(m, 23, H=0.0, amp_h=0.2, amp_u=0.05)
+    dt = 0.2 * m.dcEdge.min() / math.sqrt(9.81 * 500.0) * 6
+    return m, cases, o, h + h2, u + u2, dt
+
+
+@pytest.mark.parametrize("case", ["inner_f", "inner_i1", "inner_c", "outer_i1"])
+def test_wide_cell_multilevel(wide_levels, case):
+    """Three-level LTS3 (ratios 2 and 3) with the 11-gon in each part of the
+    nested regions: FP64 parity with the oracle's multi-level step."""
+    m, cases, o, h, u, dt = wide_levels
+    masks = cases[case][0]
+    say("wide multilevel", case)
+    c = lts.LTSContext(0, "fp64")
+    c.upload_mesh_levels(m, masks, 2, 2)
+    c.init_state(h, u)
+    c.step_levels(dt, (2, 3), 4)
+    gh, gu = c.get_state()
+    c.close()
+    rh, ru = o.mlts(h, u, dt, [2, 3], o.ml_regions(masks, 2, 2), n=4)
+    eh, eu = rel_l2(gh, rh, m.areaCell), rel_l2(gu, ru, m.dvEdge * m.dcEdge)
+    say("rel L2 h u", eh, eu)
+    assert eh < 1e-12 and eu < 1e-11

@@ -295,6 +295,18 @@ lts_status lts_ens_create(lts_ens **out, int device, lts_precision prec, void *h
 lts_status lts_ens_add_member(lts_ens *ens, const lts_mesh *mesh, const uint8_t *fine_mask,
                               int n_if1_rings, int n_if2_rings, double gravity, double dt_coarse,
                               int M, int *member);
+/* Add a multi-level member (Remark 3.1; mesh, masks and rings as
+   lts_upload_mesh_levels, M[l] for l = 0 .. n_fine_levels - 1 as
+   lts_step_levels): each ensemble step advances it by one multi-level coarse
+   step, its passes batched with the other members' (results equal
+   lts_step_levels on the member alone).  In the SSPRK3 mode
+   (lts_ens_set_scheme) it takes prod M[l] steps of dt_coarse / prod M[l].
+   LTS_EINVAL for a NULL M or a ratio < 1; labelling errors as
+   lts_upload_mesh_levels; LTS_ESTATE after lts_ens_build. */
+lts_status lts_ens_add_member_levels(lts_ens *ens, const lts_mesh *mesh, int n_fine_levels,
+                                     const uint8_t *fine_masks, int n_if1_rings,
+                                     int n_if2_rings, double gravity, double dt_coarse,
+                                     const int32_t *M, int *member);
 /* Host state of one member (caller numbering), as lts_init_state. */
 lts_status lts_ens_init_member(lts_ens *ens, int member, const double *h, const double *u);
 /* Plan the work lists, autotune when autotune != 0 (member states are

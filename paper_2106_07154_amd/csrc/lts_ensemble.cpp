@@ -36,6 +36,7 @@ struct lts_ens {
     std::vector<lts_ctx*> members;
     std::vector<double> dt;
     std::vector<int> M, sclass;
+    std::vector<std::vector<int>> Ms;  // multi-level members: ratios per level (else empty)
     bool built = false;
     int n_cu = 256;
     // tuned launch shape per [kernel class][class]: block size, grid factor
@@ -108,13 +109,22 @@ struct Builder {
             Run<T> r{c, dm, e->stream, false};
             r.rec = &recs[j];
             lts_status st = LTS_OK;
-            if (e->scheme == SCH_LTS3) st = r.lts3_step(e->dt[j], e->M[j]);
+            if (e->scheme == SCH_LTS3 && c->lv.size() > 1)
+                st = r.level_step(0, e->dt[j], e->Ms[j].data(), 0);
+            else if (e->scheme == SCH_LTS3) st = r.lts3_step(e->dt[j], e->M[j]);
             else
                 for (int k = 0; k < e->M[j] && !st; ++k) st = r.rk3_step(e->dt[j] / e->M[j]);
             if (st) return efail(e, st, "recording member " + std::to_string(j) + ": " + c->err);
             nphase = std::max(nphase, (int)recs[j].size());
         }
         return LTS_OK;
+    }
+
+    // Algorithmic bytes of kernel class k of a recorded pass.
+    static double record_bytes(const PassRecord<T>& r, int k) {
+        if (k != KC_EDGE) return kernel_bytes<T>(r.plan, k, r.cs0, r.cs1, r.aux);
+        return kernel_bytes<T>(r.plan, k, r.es0, r.es1, r.aux) +
+               kernel_bytes<T>(PassPlan(), k, Seg<T>(), Seg<T>(), r.aux2);
     }
 
     // Work items of one launch (sc < 0: members of every class); returns the
@@ -126,7 +136,7 @@ struct Builder {
             if ((sc >= 0 && e->sclass[j] != sc) || t >= (int)recs[j].size()) continue;
             lts_ctx* c = e->members[j];
             const PassRecord<T>& r = recs[j][t];
-            const PassPlan& P = c->plan[r.kind];
+            const PassPlan& P = r.plan;
             Item<T> w;
             w.m = *static_cast<DevMesh<T>*>(c->dm);
             w.h = r.h;
@@ -152,13 +162,15 @@ struct Builder {
                 w.s0 = r.es0;
                 w.s1 = r.es1;
                 w.aux = r.aux;
+                w.aux2 = r.aux2;
                 n = P.et_hi - P.et_lo;
                 if (r.aux.kind) w.nblk_aux = (int)((r.aux.nh + r.aux.nu + block - 1) / block);
+                if (r.aux2.kind) w.nblk_aux2 = (int)((r.aux2.nh + r.aux2.nu + block - 1) / block);
             }
             w.nblk = (int)((n + block - 1) / block);
-            if (w.nblk + w.nblk_aux == 0) continue;
+            if (w.nblk + w.nblk_aux + w.nblk_aux2 == 0) continue;
             w.first = first;
-            first += w.nblk + w.nblk_aux;
+            first += w.nblk + w.nblk_aux + w.nblk_aux2;
             out.push_back(w);
         }
         return first;
@@ -282,12 +294,8 @@ struct Builder {
         e->launches.clear();
         for (int k = 0; k < KC_N; ++k) e->step_bytes[k] = 0;
         for (size_t j = 0; j < recs.size(); ++j)
-            for (const PassRecord<T>& r : recs[j]) {
-                const PassPlan& P = e->members[j]->plan[r.kind];
-                e->step_bytes[KC_VERTEX] += kernel_bytes<T>(P, KC_VERTEX, r.cs0, r.cs1, r.aux);
-                e->step_bytes[KC_CELL] += kernel_bytes<T>(P, KC_CELL, r.cs0, r.cs1, r.aux);
-                e->step_bytes[KC_EDGE] += kernel_bytes<T>(P, KC_EDGE, r.es0, r.es1, r.aux);
-            }
+            for (const PassRecord<T>& r : recs[j])
+                for (int k = 0; k < KC_N; ++k) e->step_bytes[k] += record_bytes(r, k);
         if (e->fused) return finalize_fused();
         for (int sc = 0; sc < lts_ens::NCLS; ++sc)
             for (int t = 0; t < nphase; ++t)
@@ -299,10 +307,7 @@ struct Builder {
                     L.bytes = 0.0;
                     for (size_t j = 0; j < recs.size(); ++j) {
                         if (e->sclass[j] != sc || t >= (int)recs[j].size()) continue;
-                        const PassRecord<T>& r = recs[j][t];
-                        const PassPlan& P = e->members[j]->plan[r.kind];
-                        L.bytes += k == KC_EDGE ? kernel_bytes<T>(P, k, r.es0, r.es1, r.aux)
-                                                : kernel_bytes<T>(P, k, r.cs0, r.cs1, r.aux);
+                        L.bytes += record_bytes(recs[j][t], k);
                     }
                     L.sc = sc;
                     L.kclass = k;
@@ -353,21 +358,45 @@ lts_status build(lts_ens* e, int autotune) {
     lts_status st = b.record();
     if (st) return st;
     if (autotune && !e->fused) {
-        // tuning launches advance the members: keep their states and restore them
-        std::vector<std::vector<double>> h(e->members.size()), u(e->members.size());
-        for (size_t j = 0; j < e->members.size(); ++j) {
-            h[j].resize(e->members[j]->nC);
-            u[j].resize(e->members[j]->nE);
-            if ((st = lts_get_state(e->members[j], h[j].data(), u[j].data())))
-                return efail(e, st, e->members[j]->err);
-        }
-        if ((st = b.autotune())) return st;
-        EHIP(e, hipStreamSynchronize(e->stream));
-        for (size_t j = 0; j < e->members.size(); ++j) {
+        // tuning launches advance the members: keep a device copy of every
+        // member's state and copy it back afterwards, bit for bit (a round trip
+        // through lts_get_state / lts_init_state would re-derive an FP32
+        // member's reference thickness and round its perturbation anew)
+        const size_t nm = e->members.size();
+        std::vector<void*> keep(2 * nm, nullptr);
+        auto release = [&]() {
+            for (void* p : keep)
+                if (p) (void)hipFree(p);
+        };
+        for (size_t j = 0; j < nm && st == LTS_OK; ++j) {
             lts_ctx* c = e->members[j];
-            const double t0 = c->t;
-            if ((st = lts_init_state(c, h[j].data(), u[j].data(), t0))) return efail(e, st, c->err);
+            const size_t bh = (size_t)c->nC * c->L * tsize(c), bu = (size_t)c->nE * c->L * tsize(c);
+            if (hipMalloc(&keep[2 * j], bh) != hipSuccess ||
+                hipMalloc(&keep[2 * j + 1], bu) != hipSuccess ||
+                hipMemcpyAsync(keep[2 * j], c->Ah, bh, hipMemcpyDeviceToDevice, e->stream) !=
+                    hipSuccess ||
+                hipMemcpyAsync(keep[2 * j + 1], c->Au, bu, hipMemcpyDeviceToDevice, e->stream) !=
+                    hipSuccess)
+                st = efail(e, LTS_ENOMEM, "autotune: keeping the member states");
         }
+        if (st == LTS_OK) st = b.autotune();
+        if (st == LTS_OK && hipStreamSynchronize(e->stream) != hipSuccess)
+            st = efail(e, LTS_EDEVICE, "autotune: synchronise");
+        for (size_t j = 0; j < nm && st == LTS_OK; ++j) {
+            lts_ctx* c = e->members[j];
+            const size_t bh = (size_t)c->nC * c->L * tsize(c), bu = (size_t)c->nE * c->L * tsize(c);
+            if (hipMemcpyAsync(c->Ah, keep[2 * j], bh, hipMemcpyDeviceToDevice, e->stream) !=
+                    hipSuccess ||
+                hipMemcpyAsync(c->Au, keep[2 * j + 1], bu, hipMemcpyDeviceToDevice, e->stream) !=
+                    hipSuccess ||
+                launch_fill_int(c->flag, 0, e->stream) != hipSuccess)
+                st = efail(e, LTS_EDEVICE, "autotune: restoring the member states");
+            c->nonfinite = false;
+        }
+        if (hipStreamSynchronize(e->stream) != hipSuccess && st == LTS_OK)
+            st = efail(e, LTS_EDEVICE, "autotune: synchronise");
+        release();
+        if (st) return st;
     }
     return b.finalize();
 }
@@ -532,6 +561,41 @@ lts_status lts_ens_add_member(lts_ens* e, const lts_mesh* mesh, const uint8_t* f
     e->members.push_back(c);
     e->dt.push_back(dt_coarse);
     e->M.push_back(M);
+    e->Ms.emplace_back();
+    e->sclass.push_back(member_class(c->nC, padded_slots(c->maxE)));
+    if (member) *member = (int)e->members.size() - 1;
+    return LTS_OK;
+}
+
+lts_status lts_ens_add_member_levels(lts_ens* e, const lts_mesh* mesh, int n_fine_levels,
+                                     const uint8_t* fine_masks, int n_if1_rings,
+                                     int n_if2_rings, double gravity, double dt_coarse,
+                                     const int32_t* M, int* member) {
+    lts_status s = ens_ready(e);
+    if (s) return s;
+    if (e->built) return efail(e, LTS_ESTATE, "ensemble already built");
+    if (!mesh || !M || !(dt_coarse > 0) || n_fine_levels < 1)
+        return efail(e, LTS_EINVAL, "bad member arguments");
+    long prod = 1;
+    for (int l = 0; l < n_fine_levels; ++l) {
+        if (M[l] < 1) return efail(e, LTS_EINVAL, "bad member arguments: a ratio < 1");
+        prod = std::min(prod * M[l], 1L << 20);
+    }
+    lts_ctx* c = nullptr;
+    if ((s = lts_create(&c, e->device, e->prec, e->stream))) return efail(e, s, "member context");
+    if ((s = lts_upload_mesh_levels(c, mesh, n_fine_levels, fine_masks, n_if1_rings,
+                                    n_if2_rings, gravity))) {
+        const std::string msg = c->err;
+        lts_destroy(c);
+        return efail(e, s, "member mesh: " + msg);
+    }
+    e->members.push_back(c);
+    e->dt.push_back(dt_coarse);
+    // the SSPRK3 mode steps a multi-level member at its finest step
+    e->M.push_back((int)prod);
+    e->Ms.emplace_back(n_fine_levels > 1 ? std::vector<int>(M, M + n_fine_levels)
+                                         : std::vector<int>());
+    if (n_fine_levels == 1) e->M.back() = M[0];
     e->sclass.push_back(member_class(c->nC, padded_slots(c->maxE)));
     if (member) *member = (int)e->members.size() - 1;
     return LTS_OK;

@@ -126,11 +126,11 @@ lts_status dalloc(lts_ctx* c, void** p, size_t bytes);
 // batches the passes of many members into shared launches).
 template <typename T>
 struct PassRecord {
-    int kind;
+    PassPlan plan;
     const T* h;
     const T* u;
     Seg<T> cs0, cs1, es0, es1;
-    Aux<T> aux;
+    Aux<T> aux, aux2;
 };
 
 // ---------------------------------------------------------------- launches
@@ -205,10 +205,6 @@ struct Run {
     // One right-hand-side pass of kind p over state (h, u) with epilogues.
     lts_status pass(int p, const T* h, const T* u, const Seg<T>& cs0, const Seg<T>& cs1,
                     const Seg<T>& es0, const Seg<T>& es1, const Aux<T>& aux = Aux<T>()) {
-        if (rec) {
-            rec->push_back(PassRecord<T>{p, h, u, cs0, cs1, es0, es1, aux});
-            return LTS_OK;
-        }
         return pass_plan(c->plan[p], h, u, cs0, cs1, es0, es1, aux);
     }
 
@@ -216,6 +212,10 @@ struct Run {
     lts_status pass_plan(const PassPlan& P, const T* h, const T* u, const Seg<T>& cs0,
                          const Seg<T>& cs1, const Seg<T>& es0, const Seg<T>& es1,
                          const Aux<T>& aux, const Aux<T>& aux2 = Aux<T>()) {
+        if (rec) {
+            rec->push_back(PassRecord<T>{P, h, u, cs0, cs1, es0, es1, aux, aux2});
+            return LTS_OK;
+        }
         T* q = static_cast<T*>(c->q);
         T* zs = static_cast<T*>(c->zs);
         hipEvent_t e0, e1;

@@ -123,9 +123,9 @@ struct Item {
     T* zs = nullptr;
     int* flag = nullptr;
     T g = 0;
-    int lo = 0, hi = 0, nblk = 0, nblk_aux = 0, first = 0;
+    int lo = 0, hi = 0, nblk = 0, nblk_aux = 0, nblk_aux2 = 0, first = 0;
     Seg<T> s0, s1;
-    Aux<T> aux;
+    Aux<T> aux, aux2;  // edge items: appended element-wise jobs (blocks after the edges)
 };
 
 template <typename T>

@@ -436,9 +436,9 @@ __global__ __launch_bounds__(kBlock) void k_edge(const T* __restrict__ zs, int n
 
 // ---------------------------------------------------------------------------
 // Batched (ensemble) kernels.  A launch carries a work list: item k covers
-// virtual blocks [first_k, first_k + nblk_k + nblk_aux_k) of one member's
-// range.  The grid is persistent (fixed size, chosen by the autotuner); each
-// block finds its item by binary search.
+// virtual blocks [first_k, first_k + nblk_k + nblk_aux_k + nblk_aux2_k) of one
+// member's range.  The grid is persistent (fixed size, chosen by the
+// autotuner); each block finds its item by binary search.
 //
 // Virtual blocks [0, nvb) are split into one contiguous chunk per XCD, sized
 // by the XCD's share of the grid (blocks are dispatched round-robin over the
@@ -506,8 +506,10 @@ __global__ __launch_bounds__(512) void kb_edge(const Item<T>* __restrict__ items
         if (k < w.nblk) {
             const int e = w.lo + k * (int)blockDim.x + threadIdx.x;
             if (e < w.hi) edge_body(w.zs, w.m.nE, e, w.s0, w.s1, w.flag);
-        } else {
+        } else if (k < w.nblk + w.nblk_aux) {
             run_aux(w.aux, (k - w.nblk) * (int)blockDim.x + threadIdx.x);
+        } else {
+            run_aux(w.aux2, (k - w.nblk - w.nblk_aux) * (int)blockDim.x + threadIdx.x);
         }
     }
 }
@@ -675,8 +677,10 @@ __global__ __launch_bounds__(256) void kf_step(const Item<T>* __restrict__ items
                 } else if (j < w.nblk) {
                     const int e = w.lo + lt;
                     if (e < w.hi) edge_body(w.zs, w.m.nE, e, w.s0, w.s1, w.flag);
-                } else {
+                } else if (j < w.nblk + w.nblk_aux) {
                     run_aux(w.aux, (j - w.nblk) * (int)blockDim.x + threadIdx.x);
+                } else {
+                    run_aux(w.aux2, (j - w.nblk - w.nblk_aux) * (int)blockDim.x + threadIdx.x);
                 }
             }
             if (!grid_barrier(bar, bc, limit)) return;

@@ -26,7 +26,8 @@ EXPORTED = ["lts_create", "lts_set_layers", "lts_upload_mesh", "lts_upload_mesh_
             "lts_init_state_device", "lts_step", "lts_step_rk3", "lts_step_scheme", "lts_eval_rhs",
             "lts_diagnostics", "lts_get_state", "lts_get_state_device", "lts_set_timing",
             "lts_kernel_stats", "lts_region_counts", "lts_plan", "lts_last_error", "lts_destroy",
-            "lts_ens_create", "lts_ens_add_member", "lts_ens_init_member", "lts_ens_build",
+            "lts_ens_create", "lts_ens_add_member", "lts_ens_add_member_levels",
+            "lts_ens_init_member", "lts_ens_build",
             "lts_ens_step", "lts_ens_set_scheme", "lts_ens_set_fused", "lts_ens_kernel_stats",
             "lts_ens_get_member",
             "lts_ens_diagnostics", "lts_ens_info",
@@ -121,6 +122,8 @@ def load_library(path: str = LIB_PATH):
         "lts_ens_create": ([PP, ci, ci, P], ci),
         "lts_ens_add_member": ([P, ctypes.POINTER(_Mesh), P, ci, ci, cd, cd, ci,
                                ctypes.POINTER(ctypes.c_int)], ci),
+        "lts_ens_add_member_levels": ([P, ctypes.POINTER(_Mesh), ci, P, ci, ci, cd, cd, P,
+                                      ctypes.POINTER(ctypes.c_int)], ci),
         "lts_ens_init_member": ([P, ci, P, P], ci),
         "lts_ens_build": ([P, ci], ci),
         "lts_ens_step": ([P, ci], ci),
@@ -477,6 +480,23 @@ class Ensemble:
         self._check(self._lib.lts_ens_add_member(self._h, ctypes.byref(m), _ptr(fm), int(n_if1),
                                                  int(n_if2), float(gravity), float(dt_coarse),
                                                  int(M), ctypes.byref(idx)))
+        self.meshes.append(mesh)
+        return idx.value
+
+    def add_member_levels(self, mesh, fine_masks, dt_coarse, Ms, n_if1=2, n_if2=2,
+                          gravity=9.81, use_positions=True) -> int:
+        """Multi-level member: nested fine masks, outermost first, and the
+        step ratio Ms[l] of level l to level l+1 (Remark 3.1)."""
+        m, keep = _mesh_struct(mesh, use_positions)
+        fm = np.ascontiguousarray(np.stack([np.asarray(x, np.uint8) for x in fine_masks]))
+        Ma = np.ascontiguousarray(Ms, np.int32)
+        if Ma.shape != (fm.shape[0],):
+            raise ValueError("one ratio per fine level")
+        idx = ctypes.c_int()
+        self._check(self._lib.lts_ens_add_member_levels(self._h, ctypes.byref(m), fm.shape[0],
+                                                        _ptr(fm), int(n_if1), int(n_if2),
+                                                        float(gravity), float(dt_coarse),
+                                                        _ptr(Ma), ctypes.byref(idx)))
         self.meshes.append(mesh)
         return idx.value
 

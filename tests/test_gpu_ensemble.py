@@ -258,3 +258,89 @@ def test_fused_barrier_that_gives_up_is_an_error(members):
         assert np.array_equal(ha, hb) and np.array_equal(ua, ub), j
     a.close()
     b.close()
+
+
+@pytest.fixture(scope="module")
+def level_members():
+    """Two multi-level members (nested strips on a 48 x 48 hexagonal mesh,
+    three levels; nested disks on an irregular 32 x 32 Voronoi mesh, three
+    levels) and a two-level member, with their states and steps."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07154_amd.inputs import igw_parameters, igw_state, strip_fine_mask
+    from paper_2106_07154_amd.inputs.voronoi_planar import (jittered_hex_points,
+                                                            periodic_voronoi_mesh)
+    out = []
+    n, dc = 48, 20e3
+    m = periodic_hex_mesh(n, n, dc, f0=1e-4)
+    h, u = igw_state(m, igw_parameters(m, amp=20.0), 0.0)
+    out.append((m, [strip_fine_mask(m, 6, 41, dc), strip_fine_mask(m, 18, 29, dc)], h, u, 60.0,
+                (2, 3)))
+    p, Lx, Ly = jittered_hex_points(32, 32, 1.0e4, 0.55, seed=58)
+    m = periodic_voronoi_mesh(p, Lx, Ly, f0=1.0e-4, name="irregular32")
+    m.bottom = 20.0 * np.random.default_rng(32).standard_normal(m.nCells)
+    cx, cy = m.Lx / 2, m.Ly / 2
+    masks = [disk_fine_mask(m, cx, cy, 1.2e5), disk_fine_mask(m, cx + 1e4, cy, 2.5e4)]
+    h, u = gaussian_bump_state(m, 500.0, 3.0, 0.1 * m.Lx, cx, cy)
+    h2, u2 = random_state(m, 6, H=0.0, amp_h=0.05, amp_u=0.02)
+    dt = 0.3 * m.dcEdge.min() / math.sqrt(9.81 * 500.0) * 2
+    out.append((m, masks, h + h2, u + u2, dt, (2, 2)))
+    m = periodic_hex_mesh(64, 64, 10e3, f0=1e-4)
+    h, u = gaussian_bump_state(m, 500.0, 3.0, 0.1 * m.Lx, m.Lx / 2, m.Ly / 2)
+    dt = 0.3 * m.dcEdge.min() / math.sqrt(9.81 * 500.0)
+    out.append((m, [disk_fine_mask(m, m.Lx / 2, m.Ly / 2, 0.15 * m.Lx)], h, u, dt, (4,)))
+    return out
+
+
+def _level_ensemble(level_members, prec, fused=False):
+    ens = lts.Ensemble(0, prec)
+    for m, masks, h, u, dt, Ms in level_members:
+        ens.add_member_levels(m, masks, dt, Ms)
+    for j, (m, masks, h, u, dt, Ms) in enumerate(level_members):
+        ens.init_member(j, h, u)
+    if fused:
+        ens.set_fused(True)
+    ens.build(autotune=not fused)
+    return ens
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multilevel_members(level_members, prec):
+    """Multi-level members (Remark 3.1) batched with a two-level one: every
+    member equals lts_step_levels / lts_step on the member alone to rounding
+    (the batched cell kernel loads its epilogue operands after the tendency,
+    so the compiled arithmetic may round differently; the tolerances of the
+    two-level ensemble test), the fused step equals the batched launches
+    bitwise, and in FP64 each member matches the oracle's multi-level step."""
+    say("ensemble multilevel members", prec, [m.nCells for m, *_ in level_members])
+    ens = _level_ensemble(level_members, prec)
+    ens.step(3)
+    fz = _level_ensemble(level_members, prec, fused=True)
+    fz.step(3)
+    for j, (m, masks, h, u, dt, Ms) in enumerate(level_members):
+        gh, gu = ens.get_member(j)
+        c = lts.LTSContext(0, prec)
+        c.upload_mesh_levels(m, masks, 2, 2)
+        c.init_state(h, u)
+        if len(masks) > 1:
+            c.step_levels(dt, Ms, 3)
+        else:
+            c.step(dt, Ms[0], 3)
+        rh, ru = c.get_state()
+        c.close()
+        eh, eu = rel_l2(gh, rh), rel_l2(gu, ru)
+        say("member", j, m.nCells, "levels", len(masks) + 1, "against the member alone", eh, eu)
+        tol = 1e-14 if prec == "fp64" else 1e-6
+        assert eh <= tol and eu <= tol * 10, j
+        fh, fu = fz.get_member(j)
+        assert np.array_equal(fh, gh) and np.array_equal(fu, gu), j
+        assert ens.diagnostics(j).steps == 3
+        if prec == "fp64":
+            o = Oracle(m)
+            oh, ou = o.mlts(h, u, dt, list(Ms), o.ml_regions(masks, 2, 2), n=3)
+            eh, eu = rel_l2(gh, oh), rel_l2(gu, ou)
+            say("member", j, "oracle rel L2 h", eh, "u", eu)
+            assert eh < 1e-12 and eu < 1e-11, j
+    ens.close()
+    fz.close()

@@ -301,7 +301,8 @@ lts_status lts_ens_add_member(lts_ens *ens, const lts_mesh *mesh, const uint8_t 
    step, its passes batched with the other members' (results equal
    lts_step_levels on the member alone).  In the SSPRK3 mode
    (lts_ens_set_scheme) it takes prod M[l] steps of dt_coarse / prod M[l].
-   LTS_EINVAL for a NULL M or a ratio < 1; labelling errors as
+   LTS_EINVAL for a NULL M, a ratio < 1, ratios whose product exceeds 2^20 or
+   n_fine_levels outside 1 .. LTS_MAX_LEVELS - 1; labelling errors as
    lts_upload_mesh_levels; LTS_ESTATE after lts_ens_build. */
 lts_status lts_ens_add_member_levels(lts_ens *ens, const lts_mesh *mesh, int n_fine_levels,
                                      const uint8_t *fine_masks, int n_if1_rings,

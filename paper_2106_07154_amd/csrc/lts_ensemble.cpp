@@ -109,7 +109,7 @@ struct Builder {
             Run<T> r{c, dm, e->stream, false};
             r.rec = &recs[j];
             lts_status st = LTS_OK;
-            if (e->scheme == SCH_LTS3 && c->lv.size() > 1)
+            if (e->scheme == SCH_LTS3 && !e->Ms[j].empty())
                 st = r.level_step(0, e->dt[j], e->Ms[j].data(), 0);
             else if (e->scheme == SCH_LTS3) st = r.lts3_step(e->dt[j], e->M[j]);
             else
@@ -574,12 +574,15 @@ lts_status lts_ens_add_member_levels(lts_ens* e, const lts_mesh* mesh, int n_fin
     lts_status s = ens_ready(e);
     if (s) return s;
     if (e->built) return efail(e, LTS_ESTATE, "ensemble already built");
-    if (!mesh || !M || !(dt_coarse > 0) || n_fine_levels < 1)
+    if (!mesh || !M || !(dt_coarse > 0) || n_fine_levels < 1 ||
+        n_fine_levels > LTS_MAX_LEVELS - 1)
         return efail(e, LTS_EINVAL, "bad member arguments");
-    long prod = 1;
+    long prod = 1;  // the finest level's steps per coarse step
     for (int l = 0; l < n_fine_levels; ++l) {
         if (M[l] < 1) return efail(e, LTS_EINVAL, "bad member arguments: a ratio < 1");
-        prod = std::min(prod * M[l], 1L << 20);
+        prod *= M[l];
+        if (prod > (1L << 20))
+            return efail(e, LTS_EINVAL, "bad member arguments: the ratios multiply beyond 2^20");
     }
     lts_ctx* c = nullptr;
     if ((s = lts_create(&c, e->device, e->prec, e->stream))) return efail(e, s, "member context");

@@ -344,3 +344,20 @@ def test_multilevel_members(level_members, prec):
             assert eh < 1e-12 and eu < 1e-11, j
     ens.close()
     fz.close()
+
+
+def test_multilevel_member_errors(level_members):
+    m, masks, h, u, dt, Ms = level_members[0]
+    say("ensemble multilevel member errors")
+    ens = lts.Ensemble(0, "fp64")
+    for bad in ((2, 0), (1 << 11, 1 << 10)):
+        with pytest.raises(lts.LTSError) as ei:
+            ens.add_member_levels(m, masks, dt, bad)
+        assert ei.value.status == lts.LTS_EINVAL, bad
+    with pytest.raises(ValueError):
+        ens.add_member_levels(m, masks, dt, (2,))       # one ratio per fine level
+    with pytest.raises(lts.LTSError) as ei:              # nesting too close: the upload's error
+        ens.add_member_levels(m, [masks[0], masks[0]], dt, (2, 2))
+    assert ei.value.status == lts.LTS_ELABEL
+    assert ens.add_member_levels(m, masks, dt, Ms) == 0
+    ens.close()

@@ -36,6 +36,9 @@ namespace lts {
 namespace {
 
 constexpr int kBlock = 256;
+// Smallest pass (cells) whose FP64 single-range cell kernel takes the shared
+// per-cell loads (cell_share_loads).
+constexpr int kShareMinCells = 1 << 17;
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so every XCD works
 // on one contiguous chunk of the range and neighbouring blocks share its L2.
@@ -242,6 +245,49 @@ __device__ __forceinline__ void hold(T& x) {
     asm volatile("" : "+v"(x));
 }
 
+// The per-cell operands of a wave's 8 cells (h_i, S_n, beta_i, 1/A_i, the
+// three epilogue operands and, when present, href_i) in one vector load:
+// lane k reads array k / 8 of the wave's cell k % 8 into lds[threadIdx.x].
+// Every lane of a cell needs these values, and read per lane they took
+// seven or eight load instructions of the 8-lane layout; the address and data
+// units' work grows with the instructions and the bytes each lane requests,
+// not with the distinct lines, so one load plus an exchange through LDS
+// relieves the units that bound the cell kernel.
+template <typename T, int HR>
+__device__ __forceinline__ void cell_share_loads(const DevMesh<T>& m, const T* __restrict__ h,
+                                                 int c_lo, int c_hi, int t, const Seg<T>& s0,
+                                                 const Seg<T>& s1, T* __restrict__ lds) {
+    const int k = t & 63;
+    const int a = k >> 3;
+    int j = c_lo + (t & ~63) / 8 + (k & 7);
+    j = j < c_hi ? j : c_hi - 1;  // dead cells shadow a valid one, as in cell_body
+    // the epilogue operands' addresses, as epi_loads takes them
+    const bool in0 = s0.mode && j >= s0.lo && j < s0.hi;
+    const bool in1 = !in0 && s1.mode && j >= s1.lo && j < s1.hi;
+    const T* po = in0 && s0.mode == 1 && s0.xold   ? s0.xold + j
+                  : in1 && s1.mode == 1 && s1.xold ? s1.xold + j
+                                                   : h;
+    const T* pc = in0 && s0.mode == 1 && s0.xcur   ? s0.xcur + j
+                  : in1 && s1.mode == 1 && s1.xcur ? s1.xcur + j
+                                                   : h;
+    const bool a0 = in0 && !s0.first && (s0.mode != 1 || s0.acc);
+    const bool a1 = in1 && !s1.first && (s1.mode != 1 || s1.acc);
+    const T* pa = a0 ? s0.acc + (j - s0.lo) : a1 ? s1.acc + (j - s1.lo) : h;
+    const T* p = a == 0   ? h + j
+                 : a == 1 ? m.sn + j
+                 : a == 2 ? m.beta + j
+                 : a == 3 ? m.rarea + j
+                 : a == 4 ? po
+                 : a == 5 ? pc
+                 : a == 6 ? pa
+                          : (present<HR>(m.href) ? m.href + j : h);
+    lds[threadIdx.x] = *p;
+    // the wave's own LDS writes are visible to its later reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One cell lane between its loads and its arithmetic.
 template <typename T>
 struct CellLane {
@@ -255,11 +301,14 @@ struct CellLane {
 // Loads of lane `lane` of cell i (a valid cell; live: the lane's own cell is
 // in the pass range).  HR: presence of m.href (see present).  PRE: the
 // epilogue's operands are loaded here too (epi_loads), not after the
-// tendency.
-template <typename T, int G, int HR, bool PRE>
+// tendency.  SH (8-lane single-range kernel): the per-cell operands come from
+// lds as cell_share_loads left them (array a of the cell at a * 8 + the
+// cell's place in its wave).
+template <typename T, int G, int HR, bool PRE, bool SH = false>
 __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* __restrict__ h,
                                                   const T* __restrict__ u, int i, int lane,
-                                                  bool live, const Seg<T>& s0, const Seg<T>& s1) {
+                                                  bool live, const Seg<T>& s0, const Seg<T>& s1,
+                                                  const T* __restrict__ lds = nullptr) {
     CellLane<T> c;
     const T* __restrict__ href = m.href;
     const bool hr = present<HR>(href);
@@ -276,17 +325,23 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     c.kc = lane < so.y ? m.kc[c.o] : T(0);
     c.sb = m.sb[c.o];
     c.nd = m.nd[c.o];
-    c.sn = m.sn[i];
-    c.hc = h[i];
-    c.hi = hr ? href[i] + c.hc : c.hc;
+    const int wb = (threadIdx.x & ~63) + ((threadIdx.x & 63) >> 3);
+    c.sn = SH ? lds[wb + 8] : m.sn[i];
+    c.hc = SH ? lds[wb] : h[i];
+    c.hi = hr ? (SH ? lds[wb + 56] : href[i]) + c.hc : c.hc;
     c.hn = hr ? href[nb] + h[nb] : h[nb];
     c.ue = u[c.e];
     // every lane of the cell reads its epilogue operands (one address per
     // cell); lane 0 applies the epilogue
     c.ep = EpiIn<T>{};
-    if (PRE) c.ep = epi_loads(i, s0, s1, h);
-    c.bi = m.beta[i];
-    c.ra = m.rarea[i];
+    if (PRE && !SH) c.ep = epi_loads(i, s0, s1, h);
+    if (SH) {
+        const bool in0 = s0.mode && i >= s0.lo && i < s0.hi;
+        const bool in1 = !in0 && s1.mode && i >= s1.lo && i < s1.hi;
+        c.ep = EpiIn<T>{lds[wb + 32], lds[wb + 40], lds[wb + 48], in0 ? 0 : in1 ? 1 : -1};
+    }
+    c.bi = SH ? lds[wb + 16] : m.beta[i];
+    c.ra = SH ? lds[wb + 24] : m.rarea[i];
     return c;
 }
 
@@ -344,15 +399,25 @@ __device__ __forceinline__ void cell_body(const DevMesh<T>& m, const T* __restri
 }
 
 // The cell kernel: 8 lanes per cell over [c_lo, c_hi), blocks spread over
-// the 8 XCDs (xcd_block).
-template <typename T, int HR>
-__global__ __launch_bounds__(kBlock) void k_cell(DevMesh<T> m, const T* __restrict__ h,
-                                                 const T* __restrict__ u,
-                                                 const T* __restrict__ q, T* __restrict__ zs,
-                                                 int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1,
-                                                 int* flag) {
-    cell_body<T, 8, HR, true>(m, h, u, q, zs, xcd_block() * kBlock + threadIdx.x, c_lo, c_hi, g,
-                              s0, s1, flag);
+// the 8 XCDs (xcd_block).  SH: the per-cell operands through
+// cell_share_loads (launches of many cells; the scalar registers it needs
+// would cost a wave per SIMD without the waves-per-EU bound).
+template <typename T, int HR, bool SH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cell(
+    DevMesh<T> m, const T* __restrict__ h, const T* __restrict__ u, const T* __restrict__ q,
+    T* __restrict__ zs, int c_lo, int c_hi, T g, Seg<T> s0, Seg<T> s1, int* flag) {
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    if (!SH) {
+        cell_body<T, 8, HR, true>(m, h, u, q, zs, t, c_lo, c_hi, g, s0, s1, flag);
+        return;
+    }
+    __shared__ T lds[kBlock];
+    cell_share_loads<T, HR>(m, h, c_lo, c_hi, t, s0, s1, lds);
+    const int ic = c_lo + t / 8;
+    const bool live = ic < c_hi;
+    const int i = live ? ic : c_hi - 1;  // dead lanes shadow a valid cell
+    const CellLane<T> c = cell_loads<T, 8, HR, true, true>(m, h, u, i, t & 7, live, s0, s1, lds);
+    cell_math<T, 8, true>(m, c, q[m.voc[c.o]], zs, g, s0, s1, flag);
 }
 
 // Meshes with cells of more than 8 edges: those cells are not handled by
@@ -1015,9 +1080,23 @@ hipError_t launch_cell(const DevMesh<T>& m, const T* h, const T* u, const T* q, 
                       flag, nbc, w_lo, w_hi);
     }
     const dim3 grid(nbc);
+    // Launches of fewer cells fill the GPU's wave slots at most about twice
+    // and are latency bound: there the LDS exchange of the shared per-cell
+    // loads lengthens each wave's chain of dependent memory operations
+    // (measured 2% slower on a 200k-cell mesh with 62k-cell fine passes).
+    // FP32 keeps the per-lane loads: a 4-byte load costs the address and
+    // data units half as much, less than the exchange's added work (measured
+    // 8% slower on the 1.6M-cell sphere with the shared loads).
+    const bool sh = sizeof(T) == 8 && c_hi - c_lo >= kShareMinCells;
     if (m.href)
-        return launch(k_cell<T, 1>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
-    return launch(k_cell<T, 0>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0, s1, flag);
+        return sh ? launch(k_cell<T, 1, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g,
+                           s0, s1, flag)
+                  : launch(k_cell<T, 1, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g,
+                           s0, s1, flag);
+    return sh ? launch(k_cell<T, 0, true>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0,
+                       s1, flag)
+              : launch(k_cell<T, 0, false>, grid, s, ev0, ev1, m, h, u, q, zs, c_lo, c_hi, g, s0,
+                       s1, flag);
 }
 
 template <typename T>

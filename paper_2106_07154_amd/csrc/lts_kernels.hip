@@ -246,7 +246,8 @@ __device__ __forceinline__ void hold(T& x) {
 }
 
 // The per-cell operands of a wave's 8 cells (h_i, S_n, beta_i, 1/A_i, the
-// three epilogue operands and, when present, href_i) in one vector load:
+// three epilogue operands and href_i when present, else the FP64 kernel's
+// slot record cso[i]) in one vector load:
 // lane k reads array k / 8 of the wave's cell k % 8 into lds[threadIdx.x].
 // Every lane of a cell needs these values, and read per lane they took
 // seven or eight load instructions of the 8-lane layout; the address and data
@@ -280,7 +281,11 @@ __device__ __forceinline__ void cell_share_loads(const DevMesh<T>& m, const T* _
                  : a == 4 ? po
                  : a == 5 ? pc
                  : a == 6 ? pa
-                          : (present<HR>(m.href) ? m.href + j : h);
+                 : present<HR>(m.href) ? m.href + j
+                 // without href the last 8 lanes bring the slot record {first, n}
+                 // (8 bytes, the width of a double)
+                 : sizeof(T) == sizeof(int2) ? reinterpret_cast<const T*>(m.cso + j)
+                                             : h;
     lds[threadIdx.x] = *p;
     // the wave's own LDS writes are visible to its later reads
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -303,7 +308,8 @@ struct CellLane {
 // epilogue's operands are loaded here too (epi_loads), not after the
 // tendency.  SH (8-lane single-range kernel): the per-cell operands come from
 // lds as cell_share_loads left them (array a of the cell at a * 8 + the
-// cell's place in its wave).
+// cell's place in its wave), the slot record too when it is 8 bytes wide and
+// no href is present.
 template <typename T, int G, int HR, bool PRE, bool SH = false>
 __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* __restrict__ h,
                                                   const T* __restrict__ u, int i, int lane,
@@ -312,7 +318,13 @@ __device__ __forceinline__ CellLane<T> cell_loads(const DevMesh<T>& m, const T* 
     CellLane<T> c;
     const T* __restrict__ href = m.href;
     const bool hr = present<HR>(href);
-    const int2 so = m.cso[i];
+    int2 so;
+    if (SH && sizeof(T) == sizeof(int2) && !present<HR>(href)) {
+        const T v = lds[(threadIdx.x & ~63) + ((threadIdx.x & 63) >> 3) + 56];
+        __builtin_memcpy(&so, &v, sizeof(so));
+    } else {
+        so = m.cso[i];
+    }
     c.n = so.y;
     // lanes past the cell's last slot re-read that slot, coefficients zeroed
     c.o = (size_t)so.x + min(lane, so.y - 1);
